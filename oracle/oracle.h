@@ -1,0 +1,92 @@
+/*
+ * CPU ORACLE for the metric-semantic mapping path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, scalar C that computes what the method computes, step by step, for
+ * parity checks of the GPU library.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the product never does.  It shares no
+ * code, header, table or constant generator with the GPU library.
+ *
+ * Method (paper Sec. IV-C): voxels of size nu with centres x = nu * v (Sec. IV-C.2),
+ * grouped in 8x8x8 blocks held in a hash; projective signed distance psi along the
+ * sensor ray, linear weight (psi + tau) / (2 tau), running weighted average with
+ * truncation (Eq. 5); per-voxel class distribution updated by a recursive Bayes
+ * filter (Eq. 6, taken here as per-class vote counts: see the label reading); marching
+ * cubes with the most probable label per vertex (end of Sec. IV-C.3).
+ */
+#ifndef MAPPING_ORACLE_H
+#define MAPPING_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OM_OK = 0, OM_INVALID = -1, OM_CAPACITY = -2, OM_BUFFER = -3, OM_NO_SCAN = -4 };
+enum { OM_MESH_DIRTY = 0, OM_MESH_ALL = 1 };
+
+typedef struct omap omap;
+
+typedef struct {
+    int64_t touched;     /* |T_k| */
+    int64_t new_blocks;  /* |N_k| */
+    int64_t updates;     /* U_k: voxels whose D, W changed */
+    int64_t votes;       /* V: label votes in the last labels call */
+    int64_t mesh_blocks; /* |M| meshed by the last extraction */
+    int64_t triangles;   /* triangles of the last extraction */
+    int64_t allocated;   /* blocks in the map */
+} om_stats;
+
+omap *om_create(float voxel, float trunc, int n_classes, int64_t max_blocks);
+void om_destroy(omap *m);
+
+/* range: rows*cols fp32 row-major; elev: rows fp32 radians, top row first; T_wl: 16 fp32
+ * row-major.  Returns OM_OK, OM_INVALID or OM_CAPACITY (frame rejected, map unchanged). */
+int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_max,
+                       const float *range, const float *T_wl);
+/* labels: height*width uint8 row-major; T_wc: 16 fp32.  Uses the last integrated scan. */
+int om_integrate_labels(omap *m, int width, int height, float fx, float fy, float cx, float cy,
+                        const uint8_t *labels, const float *T_wc);
+/* Triangle soup: pos [3*cap][3] fp32, lab [3*cap], ekey [3*cap] (nullable).
+ * *n_tris receives the count (also when the buffer is too small: OM_BUFFER). */
+int om_extract_mesh(omap *m, int mode, int64_t cap_tris, float *pos, uint8_t *lab, int64_t *ekey,
+                    int64_t *n_tris);
+
+void om_get_stats(const omap *m, om_stats *s);
+int64_t om_num_blocks(const omap *m);
+/* block coordinates of all allocated blocks, [n][3] int32, in allocation order */
+void om_block_coords(const omap *m, int32_t *out);
+/* touched blocks of the last scan, [|T_k|][3] int32 (sorted by key) */
+int64_t om_touched(const omap *m, int32_t *out, int64_t cap);
+/* copy one block's voxels (x fastest); returns 0 if absent.  Any output may be NULL.
+ * counts is [n_classes][512]. band is the last-scan band flag. */
+int om_block_data(const omap *m, int bx, int by, int bz, float *D, float *W, uint8_t *fused,
+                  uint16_t *counts, uint8_t *band);
+
+/* Blocks met by the closed fixed-point segment [Q0, Q1] (2^-16 voxel units, offset so
+ * voxel v spans [v, v+1) * 2^16): brute-force half-open slab test over the AABB. */
+int64_t om_segment_blocks(const int64_t *Q0, const int64_t *Q1, int32_t *out, int64_t cap);
+/* Fixed-point band segment of one return (for pins): writes Q0, Q1; 0 if invalid return */
+int om_ray_segment(const omap *m, int rows, int cols, const float *elev, float r_max, int row,
+                   int col, float r, const float *T_wl, int64_t *Q0, int64_t *Q1);
+/* Pixel chosen for a sensor-frame point (for pins): returns 1 and row/col, or 0 if none. */
+int om_pixel_of(int rows, int cols, const float *elev, const float *p, int *row, int *col);
+
+/* Trilinear SDF query.  mode 0: fp64 points and decisions; mode 1: the points are fp32
+ * values and the cell is chosen from the fp32 quotient x / nu.  grad nullable. */
+void om_query_sdf(const omap *m, const double *pts, int64_t n, double *sdf, double *grad,
+                  uint8_t *valid, int mode);
+/* Pose adjoint in fp64: xi [B][6] = (t, omega); pts [B][N][3] fp32.
+ * loss [B], gxi [B][6], gpts [B][N][3]; margin [B][N] (nullable): distance of x/nu
+ * from the nearest integer plane (voxel units), for ill-conditioned-point masks. */
+void om_pose_adjoint(const omap *m, const double *xi, const float *pts, int B, int64_t N,
+                     double *loss, double *gxi, double *gpts, double *margin);
+
+/* Test hooks: overwrite (creating if needed) one block's D, W, fused label and mark it
+ * and its lower neighbours dirty; the rule's triangles (edge-id triples) for a mask. */
+int om_set_block(omap *m, int bx, int by, int bz, const float *D, const float *W, const uint8_t *fused);
+int om_cube_triangles(int inside_mask, int *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
