@@ -1,0 +1,171 @@
+/*
+ * mapcore: per-frame metric-semantic mapping on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the TSDF-based volumetric mapping of "Real-Time Metric-Semantic Mapping
+ * for Autonomous Navigation in Outdoor Environments" (Jiao et al.), Sec. IV-C, in its
+ * projective-distance form: posed LiDAR range images allocate 8x8x8 voxel blocks in a
+ * spatial hash and update a truncated signed distance and weight per voxel (Eq. 5);
+ * camera label images update a per-voxel class distribution (Eq. 6); marching cubes
+ * turns the distance field into a labelled triangle mesh (end of Sec. IV-C.3).
+ *
+ * Conventions (every call):
+ *   - Voxel index v in Z^3 has its centre at x = voxel_size * v (Sec. IV-C.2); block
+ *     b = floor(v / 8) per component; a voxel's local index is x + 8 y + 64 z.
+ *   - Poses are host float[16], row-major 4x4 rigid transforms from the sensor frame to
+ *     the map frame; the rotation must be orthonormal to 1e-5 with determinant > 0 and
+ *     the last row (0, 0, 0, 1), otherwise MAP_ERR_INVALID_ARG.
+ *   - Range images: device float, rows x cols, row-major.  Column c looks along azimuth
+ *     pi - c * 2 pi / cols; row k along elevation elev_rad[k], top row first (Eq. 3).
+ *     A return is valid if finite and 0 < r <= r_max; 0 marks a dropout.
+ *   - Label images: device uint8, height x width, row-major; a value >= n_classes
+ *     (e.g. 255) is "no label".  Cameras are undistorted pinholes, z forward.
+ *   - Device buffers are borrowed: the library reads or writes them only from work
+ *     enqueued on the given stream, so they must stay alive until that work completes.
+ *     Outputs are caller-allocated.  `stream` is a hipStream_t (NULL = default stream).
+ *   - A map is not thread-safe; order all calls on one map through one stream.
+ *
+ * Status codes: every call returns MAP_OK or a negative code; the text of the last
+ * failure is available from map_last_error().
+ */
+#ifndef MAPCORE_H
+#define MAPCORE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAP_OK 0
+#define MAP_ERR_INVALID_ARG -1
+#define MAP_ERR_CAPACITY -2         /* a frame would exceed max_blocks: frame rejected */
+#define MAP_ERR_BUFFER_TOO_SMALL -3 /* mesh output capacity too small */
+#define MAP_ERR_NO_SCAN -4          /* labels before any accepted LiDAR frame */
+#define MAP_ERR_DEVICE -5           /* HIP runtime error (see map_last_error) */
+
+#define MAP_MESH_DIRTY 0 /* blocks changed since the last successful DIRTY extraction */
+#define MAP_MESH_ALL 1   /* every allocated block; leaves the dirty set untouched */
+
+typedef struct map_s map_t;
+
+typedef struct {
+    float voxel_size;   /* nu, metres (> 0) */
+    float truncation;   /* tau, metres (0 < tau <= 64 nu) */
+    int64_t max_blocks; /* capacity of the block pool (>= 1) */
+    int32_t n_classes;  /* semantic classes L (1..254) */
+    int32_t device;     /* HIP device ordinal */
+} map_params;
+
+typedef struct {
+    int32_t rows, cols;    /* rows >= 2, cols >= 8 */
+    const float *elev_rad; /* HOST pointer, rows entries, strictly decreasing, within
+                              (-pi/2, pi/2) including half a row spacing beyond each end */
+    float r_max;           /* metres */
+} lidar_model;
+
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy; /* pixel (i, j) spans [i, i+1) x [j, j+1) */
+} camera_model;
+
+typedef struct {
+    int64_t touched;     /* |T_k|: blocks met by the last frame's truncation bands */
+    int64_t new_blocks;  /* blocks the last frame allocated */
+    int64_t updates;     /* U_k: voxels whose distance and weight changed */
+    int64_t votes;       /* V_k: label votes since the last LiDAR frame (all cameras) */
+    int64_t mesh_blocks; /* blocks meshed by the last extraction */
+    int64_t triangles;   /* triangles of the last extraction */
+    int64_t allocated;   /* blocks in the map */
+    int64_t frames;      /* accepted LiDAR frames */
+} map_frame_stats;
+
+/* Create an empty map on params->device: allocates and pre-initialises the block pool
+ * (distance 0, weight 0 = unobserved, no votes, fused label 255), the block hash
+ * (power of two >= 2 max_blocks slots) and the dirty set.  Work is enqueued on
+ * `stream`; *out receives the map.  (Sec. IV-C.2: two-level voxel hashing.) */
+int map_create(const map_params *params, void *stream, map_t **out);
+
+/* Free every device and host resource of the map (NULL accepted).  Synchronises the
+ * device first. */
+void map_destroy(map_t *map);
+
+/* Integrate one LiDAR range image taken at pose T_wl (Sec. IV-C.2, Eq. 5):
+ *  1. allocation: every block met by the truncation band [max(r - tau, 0), r + tau]
+ *     of a valid return (exact test in 2^-16-voxel fixed point, half-open blocks);
+ *  2. projective TSDF: every voxel of those blocks takes the range of its nearest pixel
+ *     (exact boundary predicates, ties to the higher index), psi = r - |p|; voxels with
+ *     psi < -tau are skipped; w = min((psi + tau) / (2 tau), 1);
+ *     D <- (W D + w min(psi, tau)) / (W + w), W <- W + w.
+ * The touched blocks and their lower neighbours join the dirty set.
+ * Asynchronous: returns after enqueueing.  If the frame would allocate more than
+ * max_blocks in total, the frame is rejected on the device with the map unchanged (and
+ * later label calls are no-ops until the next accepted frame); MAP_ERR_CAPACITY is then
+ * returned by the next map_sync or map_stats. */
+int map_integrate_lidar(map_t *map, const lidar_model *lidar, const float *range_dev,
+                        const float T_wl[16], void *stream);
+
+/* Fuse one camera label image taken at pose T_wc into the voxels updated by the last
+ * accepted LiDAR frame whose |psi| <= tau (Sec. IV-C.3, Eq. 6 with hard labels): the
+ * voxel centre is projected, pixel (floor u, floor v) is read, and if its label l is
+ * below n_classes the voxel's count of l is incremented (saturating at 65535) and its
+ * most probable label is updated (largest count, ties to the lowest id).  Call once per
+ * camera.  Asynchronous.  MAP_ERR_NO_SCAN before the first LiDAR frame. */
+int map_integrate_labels(map_t *map, const camera_model *cam, const uint8_t *labels_dev,
+                         const float T_wc[16], void *stream);
+
+/* Marching cubes over blocks (end of Sec. IV-C.3): a cube whose eight corner voxels are
+ * all observed (W > 0) emits triangles on its edges whose corners differ in D < 0;
+ * each vertex lies at the linear zero crossing and carries the most probable label of
+ * its endpoint with the smaller |D| (255 = none).  Triangles face D >= 0.
+ * Outputs (device): pos [cap_tris][3][3] float, lab [cap_tris][3] uint8, and, if
+ * non-NULL, edge_keys [cap_tris][3] int64 (the voxel v and axis of each vertex's edge:
+ * ((vx + 2^19) << 42) | ((vy + 2^19) << 22) | ((vz + 2^19) << 2) | axis).
+ * Synchronises `stream` and writes the triangle count to the host *n_tris.  If it
+ * exceeds cap_tris, only cap_tris triangles are written, MAP_ERR_BUFFER_TOO_SMALL is
+ * returned and the dirty set is kept.  DIRTY mode clears the dirty set on success. */
+int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
+                     int64_t *edge_keys_dev, int64_t cap_tris, int64_t *n_tris, void *stream);
+
+/* Trilinear query of the distance field at n world points (device float [n][3]):
+ * sdf [n] float, grad [n][3] float (nullable), valid [n] uint8.  A point is valid when
+ * all eight voxels around it are observed; invalid points get 0.  Asynchronous. */
+int map_query_sdf(map_t *map, const float *pts_dev, int64_t n, float *sdf_dev, float *grad_dev,
+                  uint8_t *valid_dev, void *stream);
+
+/* Loss and adjoint of B posed scans against the map: for pose b, xi_b = (t, w) (device
+ * float [B][6]) maps the sensor-frame points p_bj (device float [B][N][3]) to
+ * y = Exp(w) p + t; loss_b = sum_j valid * D(y)^2.  Writes loss [B], dL/dxi [B][6]
+ * (translation part, then the rotation part through the SO(3) left Jacobian) and, if
+ * non-NULL, dL/dp [B][N][3].  The reduction over points is in a fixed order (bitwise
+ * reproducible).  Asynchronous. */
+int map_sdf_pose_adjoint(map_t *map, const float *xi_dev, const float *pts_dev, int32_t B,
+                         int64_t N, float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream);
+
+/* Synchronise the map's last stream and return (then clear) any deferred status. */
+int map_sync(map_t *map);
+
+/* Counters of the last frame, labels call and extraction (synchronises). */
+int map_stats(map_t *map, map_frame_stats *out);
+
+/* Message of the last failure on this map ("" if none).  With map == NULL: the last
+ * failure of map_create. */
+const char *map_last_error(const map_t *map);
+
+/* Test and benchmark access (synchronous): copy the coordinates [n][3] int32 of all
+ * allocated blocks in slot order, or the touched blocks of the last frame; returns the
+ * count (entries beyond cap are not written). */
+int64_t map_block_coords(map_t *map, int32_t *coords_host, int64_t cap);
+int64_t map_touched_coords(map_t *map, int32_t *coords_host, int64_t cap);
+/* Copy one block's voxels to host buffers (any may be NULL): D, W [512] float,
+ * fused [512] uint8, counts [n_classes][512] uint16.  Returns 1, or 0 if absent. */
+int map_read_block(map_t *map, int32_t bx, int32_t by, int32_t bz, float *D, float *W,
+                   uint8_t *fused, uint16_t *counts);
+/* Copy the first min(cap, allocated) blocks in slot order (any output may be NULL):
+ * coords [cap][3] int32, D and W [cap][512] float, fused [cap][512] uint8, counts
+ * [cap][n_classes][512] uint16.  Returns the number of allocated blocks, -1 on error. */
+int64_t map_download(map_t *map, int64_t cap, int32_t *coords, float *D, float *W,
+                     uint8_t *fused, uint16_t *counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

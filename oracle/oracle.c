@@ -520,8 +520,11 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
     for (int64_t i = 0; i < nlist; ++i)
         if (hash_find(&m->h, list[i]) < 0) n_new++;
     if (m->nblocks + n_new > m->max_blocks) {
+        /* rejected: the map is unchanged and there is no scan to label */
         free(list);
         lut_free(&t);
+        m->ntouched = 0;
+        m->st.votes = 0;
         return OM_CAPACITY;
     }
     qsort(list, nlist, sizeof(int64_t), cmp_i64);
@@ -598,6 +601,7 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
     m->st.touched = m->ntouched;
     m->st.new_blocks = n_new;
     m->st.updates = updates;
+    m->st.votes = 0;
     m->st.allocated = m->nblocks;
     return OM_OK;
 }
@@ -647,7 +651,7 @@ int om_integrate_labels(omap *m, int width, int height, float fx, float fy, floa
             votes++;
         }
     }
-    m->st.votes = votes;
+    m->st.votes += votes;
     return OM_OK;
 }
 

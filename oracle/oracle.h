@@ -30,7 +30,7 @@ typedef struct {
     int64_t touched;     /* |T_k| */
     int64_t new_blocks;  /* |N_k| */
     int64_t updates;     /* U_k: voxels whose D, W changed */
-    int64_t votes;       /* V: label votes in the last labels call */
+    int64_t votes;       /* V_k: label votes since the last LiDAR frame */
     int64_t mesh_blocks; /* |M| meshed by the last extraction */
     int64_t triangles;   /* triangles of the last extraction */
     int64_t allocated;   /* blocks in the map */

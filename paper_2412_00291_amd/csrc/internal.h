@@ -1,0 +1,152 @@
+// Internal types shared by the mapcore HIP sources (device views, launch wrappers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mc {
+
+constexpr int kBlockVoxels = 512;
+constexpr unsigned long long kEmpty = ~0ull;
+constexpr int kFxShift = 16;                  // 2^-16 voxel fixed point
+constexpr long long kBlockFx = 8LL << kFxShift;  // one block edge in fixed point
+constexpr int kDomainVoxels = (1 << 19) - 64;    // |voxel index| bound of the map domain
+
+// Device-side counters of one map.
+struct Counters {
+    int32_t n_touched;   // entries appended to the touched list this frame
+    int32_t n_new;       // of which absent from the map
+    int32_t pool_used;   // allocated blocks
+    int32_t frame_ok;    // 1 if the current frame was accepted
+    int32_t n_dirty;     // entries of the dirty list
+    uint32_t dirty_epoch;
+    int32_t status;      // deferred error (MAP_ERR_CAPACITY) until read by the host
+    int32_t frames;      // accepted frames
+    unsigned long long updates;     // U_k
+    unsigned long long votes;       // label votes since the last LiDAR frame
+    unsigned long long tris;        // triangles of the current extraction
+    unsigned long long mesh_blocks; // blocks of the current extraction
+    int32_t last_touched;  // |T_k| of the last accepted frame (labels read it)
+    int32_t last_new;
+    int32_t overflow;      // touched list overflow (cannot happen with the sizing rule)
+    int32_t pad;
+};
+
+// Block pool, hash and dirty set.
+struct MapView {
+    float2 *dw;               // [max_blocks][512] (D, W)
+    uint8_t *fused;           // [max_blocks][512]
+    uint16_t *counts;         // [max_blocks][L][512]
+    int4 *coords;             // [max_blocks] block coordinates per slot
+    unsigned long long *hkeys;  // [hmask + 1]
+    int32_t *hvals;           // [hmask + 1]
+    uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
+    int32_t *dirty_list;      // [max_blocks]
+    Counters *ctr;
+    uint32_t hmask;
+    int32_t n_classes;
+    int32_t max_blocks;
+    float nu, tau;
+};
+
+// Per-frame scratch: frame set (de-duplication of the frame's blocks) and touched list.
+struct FrameView {
+    unsigned long long *fkeys;  // [fmask + 1]
+    unsigned long long *tk_key; // [tk_cap]
+    int32_t *tk_slot;           // [tk_cap] pool slot (-1 until committed)
+    int32_t *tk_rank;           // [tk_cap] rank among new blocks
+    int32_t *tk_fslot;          // [tk_cap] frame-set slot (cleared at frame end)
+    unsigned long long *band;   // [tk_cap][8] band bits (|psi| <= tau) per voxel
+    uint32_t fmask;
+    int32_t tk_cap;
+};
+
+// Sensor look-up tables (device), fp32 values each computed once in double.
+struct LidarLUT {
+    const float *ce, *se;   // ray elevation cos / sin, [rows]
+    const float *cp, *sp;   // ray azimuth cos / sin, [cols]
+    const float *bcx, *bcy; // azimuth boundary between columns j-1 and j, [cols]
+    const float *brc, *brs; // elevation boundary j (rows + 1 of them)
+    int32_t rows, cols;
+    float r_max;
+    float cols_over_2pi;    // initial column guess scale
+};
+
+struct Pose {  // rows 0..2 of a row-major 4x4
+    float m[12];
+};
+
+struct Camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+};
+
+struct MeshOut {
+    float *pos;
+    uint8_t *lab;
+    long long *ekey;
+    long long cap;
+};
+
+// ---------------------------------------------------------------------------------
+// key packing and hashing (device + host)
+// ---------------------------------------------------------------------------------
+__host__ __device__ inline unsigned long long pack_key(int bx, int by, int bz)
+{
+    const long long bias = 1LL << 20;
+    return ((unsigned long long)(bx + bias) << 42) | ((unsigned long long)(by + bias) << 21) |
+           (unsigned long long)(bz + bias);
+}
+
+__host__ __device__ inline int3 unpack_key(unsigned long long k)
+{
+    const int bias = 1 << 20;
+    return make_int3((int)((k >> 42) & 0x1FFFFF) - bias, (int)((k >> 21) & 0x1FFFFF) - bias,
+                     (int)(k & 0x1FFFFF) - bias);
+}
+
+__host__ __device__ inline uint32_t hash_slot(unsigned long long k, uint32_t mask)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return (uint32_t)k & mask;
+}
+
+__device__ inline int hash_find(const MapView &m, unsigned long long key)
+{
+    uint32_t i = hash_slot(key, m.hmask);
+    for (uint32_t n = 0; n <= m.hmask; ++n) {
+        unsigned long long k = m.hkeys[i];
+        if (k == key) return m.hvals[i];
+        if (k == kEmpty) return -1;
+        i = (i + 1) & m.hmask;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------------
+// launch wrappers (defined in the kernel sources)
+// ---------------------------------------------------------------------------------
+hipError_t launch_init_pool(const MapView &m, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_frame_begin(const MapView &m, hipStream_t s);
+hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                        const float *range, hipStream_t s);
+hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                       const float *range, int grid, hipStream_t s);
+hipError_t launch_finish(const MapView &m, const FrameView &f, int grid, hipStream_t s);
+hipError_t launch_labels(const MapView &m, const FrameView &f, const Camera &cam, const Pose &T,
+                         const uint8_t *labels, int grid, hipStream_t s);
+hipError_t launch_mesh_begin(const MapView &m, hipStream_t s);
+hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, int grid, hipStream_t s);
+hipError_t launch_mesh_end(const MapView &m, hipStream_t s);
+hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
+                        uint8_t *valid, hipStream_t s);
+hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,
+                          float *gpts, float *partial, int nchunk, hipStream_t s);
+hipError_t launch_adjoint_reduce(const float *xi, const float *partial, int B, int nchunk,
+                                 float *loss, float *gxi, hipStream_t s);
+
+}  // namespace mc

@@ -1,0 +1,532 @@
+// Host runtime of mapcore: map object, argument checks, sensor look-up tables, scratch
+// sizing and launch sequencing behind the C ABI declared in include/mapcore.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "mapcore.h"
+
+using namespace mc;
+
+struct map_s {
+    map_params p{};
+    MapView v{};
+    FrameView f{};
+    Counters *h_ctr = nullptr;  // pinned mirror for read-back
+    hipStream_t last_stream = nullptr;
+    bool has_scan = false;
+    std::string err;
+    // LiDAR look-up tables (device) and the model they were built for
+    float *lut_buf = nullptr;
+    size_t lut_floats = 0;
+    LidarLUT lut{};
+    int lut_rows = 0, lut_cols = 0;
+    float lut_rmax = 0.0f;
+    std::vector<float> lut_elev;
+    // adjoint partial sums
+    float *partial = nullptr;
+    size_t partial_floats = 0;
+};
+
+static std::string g_create_error;
+
+static int fail(map_t *m, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (m) m->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+#define HIP_TRY(m, expr)                                                                          \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail((m), MAP_ERR_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                \
+    } while (0)
+
+static uint64_t next_pow2(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static void free_all(map_t *m)
+{
+    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.dirty_flag,
+                    m->v.dirty_list, m->v.ctr, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
+                    m->f.tk_fslot, m->f.band, m->lut_buf, m->partial};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (m->h_ctr) (void)hipHostFree(m->h_ctr);
+}
+
+// rigid transform check: finite, last row (0,0,0,1), orthonormal rotation to 1e-5, det > 0
+static bool pose_ok(const float *T)
+{
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(T[i])) return false;
+    if (T[12] != 0.0f || T[13] != 0.0f || T[14] != 0.0f || T[15] != 1.0f) return false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += (double)T[4 * k + i] * (double)T[4 * k + j];
+            if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-5) return false;
+        }
+    double det = (double)T[0] * ((double)T[5] * T[10] - (double)T[6] * T[9]) -
+                 (double)T[1] * ((double)T[4] * T[10] - (double)T[6] * T[8]) +
+                 (double)T[2] * ((double)T[4] * T[9] - (double)T[5] * T[8]);
+    return det > 0.0;
+}
+
+static Pose to_pose(const float *T)
+{
+    Pose P;
+    for (int i = 0; i < 12; ++i) P.m[i] = T[i];
+    return P;
+}
+
+extern "C" int map_create(const map_params *params, void *stream, map_t **out)
+{
+    if (!params || !out) return fail(nullptr, MAP_ERR_INVALID_ARG, "map_create: NULL argument");
+    *out = nullptr;
+    const map_params &p = *params;
+    if (!(p.voxel_size > 0.0f) || !std::isfinite(p.voxel_size) || !(p.truncation > 0.0f) ||
+        !std::isfinite(p.truncation) || p.truncation > 64.0f * p.voxel_size)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "map_create: need voxel_size > 0 and 0 < truncation <= 64 voxel_size");
+    if (p.n_classes < 1 || p.n_classes > 254)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "map_create: n_classes must be in [1, 254]");
+    if (p.max_blocks < 1 || p.max_blocks > (int64_t)1 << 30)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "map_create: max_blocks must be in [1, 2^30]");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || p.device < 0 || p.device >= ndev)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "map_create: device %d not available", p.device);
+    if (hipSetDevice(p.device) != hipSuccess)
+        return fail(nullptr, MAP_ERR_DEVICE, "map_create: hipSetDevice failed");
+
+    map_t *m = new map_s();
+    m->p = p;
+    hipStream_t s = (hipStream_t)stream;
+    m->last_stream = s;
+    const size_t nb = (size_t)p.max_blocks;
+    const uint64_t hcap = next_pow2(std::max<uint64_t>(2 * nb, 1024));
+    MapView &v = m->v;
+    v.hmask = (uint32_t)(hcap - 1);
+    v.n_classes = p.n_classes;
+    v.max_blocks = (int32_t)p.max_blocks;
+    v.nu = p.voxel_size;
+    v.tau = p.truncation;
+    auto cleanup = [&](int code) {
+        int rc = fail(nullptr, code, "map_create: %s", m->err.c_str());
+        free_all(m);
+        delete m;
+        return rc;
+    };
+#define CREATE_TRY(expr)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            m->err = std::string(#expr) + ": " + hipGetErrorString(e_);                   \
+            return cleanup(MAP_ERR_DEVICE);                                               \
+        }                                                                                 \
+    } while (0)
+    CREATE_TRY(hipMalloc(&v.dw, nb * kBlockVoxels * sizeof(float2)));
+    CREATE_TRY(hipMalloc(&v.fused, nb * kBlockVoxels));
+    CREATE_TRY(hipMalloc(&v.counts, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t)));
+    CREATE_TRY(hipMalloc(&v.coords, nb * sizeof(int4)));
+    CREATE_TRY(hipMalloc(&v.hkeys, hcap * sizeof(unsigned long long)));
+    CREATE_TRY(hipMalloc(&v.hvals, hcap * sizeof(int32_t)));
+    CREATE_TRY(hipMalloc(&v.dirty_flag, nb * sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&v.dirty_list, nb * sizeof(int32_t)));
+    CREATE_TRY(hipMalloc(&v.ctr, sizeof(Counters)));
+    CREATE_TRY(hipHostMalloc((void **)&m->h_ctr, sizeof(Counters), hipHostMallocDefault));
+    CREATE_TRY(hipMemsetAsync(v.dw, 0, nb * kBlockVoxels * sizeof(float2), s));
+    CREATE_TRY(hipMemsetAsync(v.counts, 0, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t), s));
+    CREATE_TRY(hipMemsetAsync(v.coords, 0, nb * sizeof(int4), s));
+    CREATE_TRY(hipMemsetAsync(v.dirty_flag, 0, nb * sizeof(uint32_t), s));
+    CREATE_TRY(launch_init_pool(v, s));
+    CREATE_TRY(launch_fill_u64(v.hkeys, hcap, kEmpty, s));
+    std::memset(m->h_ctr, 0, sizeof(Counters));
+    m->h_ctr->dirty_epoch = 1;
+    CREATE_TRY(hipMemcpyAsync(v.ctr, m->h_ctr, sizeof(Counters), hipMemcpyHostToDevice, s));
+    CREATE_TRY(hipStreamSynchronize(s));
+#undef CREATE_TRY
+    *out = m;
+    return MAP_OK;
+}
+
+extern "C" void map_destroy(map_t *m)
+{
+    if (!m) return;
+    (void)hipSetDevice(m->p.device);
+    (void)hipDeviceSynchronize();
+    free_all(m);
+    delete m;
+}
+
+extern "C" const char *map_last_error(const map_t *m)
+{
+    return m ? m->err.c_str() : g_create_error.c_str();
+}
+
+// Build (or reuse) the look-up tables of a LiDAR model.  Values are computed in double
+// and rounded once to fp32: ray directions from cos / sin of the row elevation and of
+// the column azimuth pi - c 2pi/C; column boundaries at pi - (c - 1/2) 2pi/C; row
+// boundaries halfway between neighbouring elevations, the outer ones half a spacing
+// beyond the first and last rows.
+static int ensure_lut(map_t *m, const lidar_model *L, hipStream_t s)
+{
+    const int R = L->rows, C = L->cols;
+    if (m->lut_buf && m->lut_rows == R && m->lut_cols == C && m->lut_rmax == L->r_max &&
+        std::memcmp(m->lut_elev.data(), L->elev_rad, R * sizeof(float)) == 0)
+        return MAP_OK;
+    for (int k = 0; k < R; ++k)
+        if (!std::isfinite(L->elev_rad[k])) return fail(m, MAP_ERR_INVALID_ARG, "lidar: non-finite elevation");
+    for (int k = 1; k < R; ++k)
+        if (!(L->elev_rad[k] < L->elev_rad[k - 1]))
+            return fail(m, MAP_ERR_INVALID_ARG, "lidar: elevations must strictly decrease (top row first)");
+    const double e0 = L->elev_rad[0], e1 = L->elev_rad[1], en = L->elev_rad[R - 1], en1 = L->elev_rad[R - 2];
+    const double top = e0 + 0.5 * (e0 - e1), bot = en - 0.5 * (en1 - en);
+    if (!(top < M_PI / 2) || !(bot > -M_PI / 2))
+        return fail(m, MAP_ERR_INVALID_ARG, "lidar: vertical field of view must stay within +-90 degrees");
+    const size_t nfl = 2 * (size_t)R + 4 * (size_t)C + 2 * ((size_t)R + 1);
+    std::vector<float> h(nfl);
+    float *ce = h.data(), *se = ce + R, *cp = se + R, *sp = cp + C, *bcx = sp + C, *bcy = bcx + C,
+          *brc = bcy + C, *brs = brc + R + 1;
+    for (int k = 0; k < R; ++k) {
+        ce[k] = (float)std::cos((double)L->elev_rad[k]);
+        se[k] = (float)std::sin((double)L->elev_rad[k]);
+    }
+    const double dphi = 2.0 * M_PI / (double)C;
+    for (int c = 0; c < C; ++c) {
+        const double phi = M_PI - (double)c * dphi;
+        cp[c] = (float)std::cos(phi);
+        sp[c] = (float)std::sin(phi);
+        const double pb = M_PI - ((double)c - 0.5) * dphi;
+        bcx[c] = (float)std::cos(pb);
+        bcy[c] = (float)std::sin(pb);
+    }
+    for (int j = 0; j <= R; ++j) {
+        double eb = j == 0 ? top : (j == R ? bot : 0.5 * ((double)L->elev_rad[j - 1] + (double)L->elev_rad[j]));
+        brc[j] = (float)std::cos(eb);
+        brs[j] = (float)std::sin(eb);
+    }
+    // the previous frame may still read the old tables
+    HIP_TRY(m, hipStreamSynchronize(s));
+    if (nfl > m->lut_floats) {
+        if (m->lut_buf) HIP_TRY(m, hipFree(m->lut_buf));
+        m->lut_buf = nullptr;
+        HIP_TRY(m, hipMalloc(&m->lut_buf, nfl * sizeof(float)));
+        m->lut_floats = nfl;
+    }
+    HIP_TRY(m, hipMemcpy(m->lut_buf, h.data(), nfl * sizeof(float), hipMemcpyHostToDevice));
+    float *d = m->lut_buf;
+    LidarLUT &lut = m->lut;
+    lut.ce = d;
+    lut.se = d + R;
+    lut.cp = d + 2 * R;
+    lut.sp = lut.cp + C;
+    lut.bcx = lut.sp + C;
+    lut.bcy = lut.bcx + C;
+    lut.brc = lut.bcy + C;
+    lut.brs = lut.brc + R + 1;
+    lut.rows = R;
+    lut.cols = C;
+    lut.r_max = L->r_max;
+    lut.cols_over_2pi = (float)((double)C / (2.0 * M_PI));
+    m->lut_rows = R;
+    m->lut_cols = C;
+    m->lut_rmax = L->r_max;
+    m->lut_elev.assign(L->elev_rad, L->elev_rad + R);
+    return MAP_OK;
+}
+
+// Touched-list capacity for a model: every return meets at most 1 + 3 (floor(L / 8) + 1)
+// blocks along a band of L = 2 tau / nu voxels (one per boundary crossing per axis).
+static int ensure_frame_scratch(map_t *m, const lidar_model *L, hipStream_t s)
+{
+    const double band_vox = 2.0 * (double)m->p.truncation / (double)m->p.voxel_size;
+    const int64_t per_ray = 1 + 3 * ((int64_t)std::floor(band_vox / 8.0) + 2);
+    const int64_t need = (int64_t)L->rows * L->cols * per_ray;
+    if (need > (int64_t)1 << 30) return fail(m, MAP_ERR_INVALID_ARG, "lidar: image too large");
+    if (m->f.tk_cap >= need) return MAP_OK;
+    HIP_TRY(m, hipStreamSynchronize(s));
+    FrameView &f = m->f;
+    void *old[] = {f.fkeys, f.tk_key, f.tk_slot, f.tk_rank, f.tk_fslot, f.band};
+    for (void *p : old)
+        if (p) HIP_TRY(m, hipFree(p));
+    f = FrameView{};
+    const uint64_t fcap = next_pow2((uint64_t)(2 * need));
+    HIP_TRY(m, hipMalloc(&f.fkeys, fcap * sizeof(unsigned long long)));
+    HIP_TRY(m, hipMalloc(&f.tk_key, need * sizeof(unsigned long long)));
+    HIP_TRY(m, hipMalloc(&f.tk_slot, need * sizeof(int32_t)));
+    HIP_TRY(m, hipMalloc(&f.tk_rank, need * sizeof(int32_t)));
+    HIP_TRY(m, hipMalloc(&f.tk_fslot, need * sizeof(int32_t)));
+    HIP_TRY(m, hipMalloc(&f.band, need * 8 * sizeof(unsigned long long)));
+    HIP_TRY(m, launch_fill_u64(f.fkeys, fcap, kEmpty, s));
+    f.fmask = (uint32_t)(fcap - 1);
+    f.tk_cap = (int32_t)need;
+    return MAP_OK;
+}
+
+static int grid_for(int64_t items, int per_block, int cap)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (int)(g < cap ? g : cap);
+}
+
+extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *range_dev, const float T_wl[16],
+                                   void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (!L || !range_dev || !T_wl || !L->elev_rad) return fail(m, MAP_ERR_INVALID_ARG, "integrate_lidar: NULL argument");
+    if (L->rows < 2 || L->cols < 8) return fail(m, MAP_ERR_INVALID_ARG, "integrate_lidar: need rows >= 2, cols >= 8");
+    if (!(L->r_max > 0.0f) || !std::isfinite(L->r_max))
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_lidar: r_max must be positive and finite");
+    if (!pose_ok(T_wl)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_lidar: pose is not a rigid transform");
+    const double lim = (double)m->p.voxel_size * kDomainVoxels;
+    for (int i = 0; i < 3; ++i)
+        if (std::fabs((double)T_wl[4 * i + 3]) + (double)L->r_max + (double)m->p.truncation >= lim)
+            return fail(m, MAP_ERR_INVALID_ARG, "integrate_lidar: scan reaches outside the map domain");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    int rc = ensure_lut(m, L, s);
+    if (rc) return rc;
+    rc = ensure_frame_scratch(m, L, s);
+    if (rc) return rc;
+    const Pose T = to_pose(T_wl);
+    HIP_TRY(m, launch_frame_begin(m->v, s));
+    HIP_TRY(m, launch_alloc(m->v, m->f, m->lut, T, range_dev, s));
+    HIP_TRY(m, launch_tsdf(m->v, m->f, m->lut, T, range_dev, grid_for(m->f.tk_cap, 1, 2048), s));
+    HIP_TRY(m, launch_finish(m->v, m->f, grid_for(m->f.tk_cap, 256, 1024), s));
+    m->last_stream = s;
+    m->has_scan = true;
+    return MAP_OK;
+}
+
+extern "C" int map_integrate_labels(map_t *m, const camera_model *cam, const uint8_t *labels_dev,
+                                    const float T_wc[16], void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (!cam || !labels_dev || !T_wc) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: NULL argument");
+    if (cam->width < 1 || cam->height < 1 || !std::isfinite(cam->fx) || !std::isfinite(cam->fy) ||
+        !std::isfinite(cam->cx) || !std::isfinite(cam->cy) || cam->fx == 0.0f || cam->fy == 0.0f)
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: bad camera model");
+    if (!pose_ok(T_wc)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: pose is not a rigid transform");
+    if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels: no LiDAR frame integrated yet");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    Camera c{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+    HIP_TRY(m, launch_labels(m->v, m->f, c, to_pose(T_wc), labels_dev, grid_for(m->f.tk_cap, 1, 2048), s));
+    m->last_stream = s;
+    return MAP_OK;
+}
+
+extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab_dev, int64_t *edge_keys_dev,
+                                int64_t cap_tris, int64_t *n_tris, void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (!n_tris || cap_tris < 0 || (mode != MAP_MESH_DIRTY && mode != MAP_MESH_ALL))
+        return fail(m, MAP_ERR_INVALID_ARG, "extract_mesh: bad mode, capacity or n_tris");
+    if (cap_tris > 0 && (!pos_dev || !lab_dev)) return fail(m, MAP_ERR_INVALID_ARG, "extract_mesh: NULL output");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
+    HIP_TRY(m, launch_mesh_begin(m->v, s));
+    HIP_TRY(m, launch_mesh(m->v, mode, out, grid_for(m->p.max_blocks, 1, 2048), s));
+    HIP_TRY(m, hipMemcpyAsync(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(m, hipStreamSynchronize(s));
+    m->last_stream = s;
+    const int64_t n = (int64_t)m->h_ctr->tris;
+    *n_tris = n;
+    if (n > cap_tris)
+        return fail(m, MAP_ERR_BUFFER_TOO_SMALL, "extract_mesh: %lld triangles, capacity %lld", (long long)n,
+                    (long long)cap_tris);
+    if (mode == MAP_MESH_DIRTY) HIP_TRY(m, launch_mesh_end(m->v, s));
+    return MAP_OK;
+}
+
+extern "C" int map_query_sdf(map_t *m, const float *pts_dev, int64_t n, float *sdf_dev, float *grad_dev,
+                             uint8_t *valid_dev, void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!pts_dev || !sdf_dev || !valid_dev)))
+        return fail(m, MAP_ERR_INVALID_ARG, "query_sdf: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    HIP_TRY(m, launch_query(m->v, pts_dev, n, sdf_dev, grad_dev, valid_dev, s));
+    m->last_stream = s;
+    return MAP_OK;
+}
+
+extern "C" int map_sdf_pose_adjoint(map_t *m, const float *xi_dev, const float *pts_dev, int32_t B, int64_t N,
+                                    float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (B < 1 || B > 65535 || N < 1 || !xi_dev || !pts_dev || !loss_dev || !gxi_dev)
+        return fail(m, MAP_ERR_INVALID_ARG, "sdf_pose_adjoint: bad arguments");
+    const int64_t nchunk = (N + 255) / 256;
+    if (nchunk > (int64_t)1 << 31) return fail(m, MAP_ERR_INVALID_ARG, "sdf_pose_adjoint: N too large");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    const size_t need = (size_t)B * nchunk * 8;
+    if (need > m->partial_floats) {
+        HIP_TRY(m, hipStreamSynchronize(m->last_stream));
+        HIP_TRY(m, hipStreamSynchronize(s));
+        if (m->partial) HIP_TRY(m, hipFree(m->partial));
+        m->partial = nullptr;
+        HIP_TRY(m, hipMalloc(&m->partial, need * sizeof(float)));
+        m->partial_floats = need;
+    }
+    HIP_TRY(m, launch_adjoint(m->v, xi_dev, pts_dev, B, N, gpts_dev, m->partial, (int)nchunk, s));
+    HIP_TRY(m, launch_adjoint_reduce(xi_dev, m->partial, B, (int)nchunk, loss_dev, gxi_dev, s));
+    m->last_stream = s;
+    return MAP_OK;
+}
+
+static int read_counters(map_t *m)
+{
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    HIP_TRY(m, hipStreamSynchronize(m->last_stream));
+    HIP_TRY(m, hipMemcpy(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost));
+    return MAP_OK;
+}
+
+static int take_status(map_t *m)
+{
+    int st = m->h_ctr->status;
+    if (st != 0) {
+        int zero = 0;
+        HIP_TRY(m, hipMemcpy((char *)m->v.ctr + offsetof(Counters, status), &zero, sizeof(int), hipMemcpyHostToDevice));
+        return fail(m, st, "a LiDAR frame was rejected: it would exceed max_blocks");
+    }
+    return MAP_OK;
+}
+
+extern "C" int map_sync(map_t *m)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    int rc = read_counters(m);
+    if (rc) return rc;
+    return take_status(m);
+}
+
+extern "C" int map_stats(map_t *m, map_frame_stats *out)
+{
+    if (!m || !out) return MAP_ERR_INVALID_ARG;
+    int rc = read_counters(m);
+    if (rc) return rc;
+    const Counters &c = *m->h_ctr;
+    out->touched = c.frame_ok ? c.last_touched : c.n_touched;
+    out->new_blocks = c.frame_ok ? c.last_new : 0;
+    out->updates = (int64_t)c.updates;
+    out->votes = (int64_t)c.votes;
+    out->mesh_blocks = (int64_t)c.mesh_blocks;
+    out->triangles = (int64_t)c.tris;
+    out->allocated = c.pool_used;
+    out->frames = c.frames;
+    return take_status(m);
+}
+
+extern "C" int64_t map_block_coords(map_t *m, int32_t *coords_host, int64_t cap)
+{
+    if (!m || read_counters(m)) return -1;
+    const int64_t n = m->h_ctr->pool_used;
+    const int64_t k = std::min(n, cap);
+    if (k > 0 && coords_host) {
+        std::vector<int4> tmp(k);
+        if (hipMemcpy(tmp.data(), m->v.coords, k * sizeof(int4), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+        for (int64_t i = 0; i < k; ++i) {
+            coords_host[3 * i] = tmp[i].x;
+            coords_host[3 * i + 1] = tmp[i].y;
+            coords_host[3 * i + 2] = tmp[i].z;
+        }
+    }
+    return n;
+}
+
+extern "C" int64_t map_touched_coords(map_t *m, int32_t *coords_host, int64_t cap)
+{
+    if (!m || read_counters(m)) return -1;
+    const int64_t n = m->h_ctr->last_touched;
+    const int64_t k = std::min(n, cap);
+    if (k > 0 && coords_host) {
+        std::vector<unsigned long long> tmp(k);
+        if (hipMemcpy(tmp.data(), m->f.tk_key, k * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+            return -1;
+        for (int64_t i = 0; i < k; ++i) {
+            int3 b = unpack_key(tmp[i]);
+            coords_host[3 * i] = b.x;
+            coords_host[3 * i + 1] = b.y;
+            coords_host[3 * i + 2] = b.z;
+        }
+    }
+    return n;
+}
+
+// Bulk download of the first min(cap, allocated) pool slots (tests and benchmarks).
+extern "C" int64_t map_download(map_t *m, int64_t cap, int32_t *coords, float *D, float *W, uint8_t *fused,
+                                uint16_t *counts)
+{
+    if (!m || read_counters(m)) return -1;
+    const int64_t n = m->h_ctr->pool_used;
+    const int64_t k = std::min(n, cap);
+    if (k <= 0) return n;
+    if (coords && map_block_coords(m, coords, k) < 0) return -1;
+    if (D || W) {
+        std::vector<float2> tmp((size_t)k * kBlockVoxels);
+        if (hipMemcpy(tmp.data(), m->v.dw, tmp.size() * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess)
+            return -1;
+        for (size_t i = 0; i < tmp.size(); ++i) {
+            if (D) D[i] = tmp[i].x;
+            if (W) W[i] = tmp[i].y;
+        }
+    }
+    if (fused && hipMemcpy(fused, m->v.fused, (size_t)k * kBlockVoxels, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    if (counts && hipMemcpy(counts, m->v.counts, (size_t)k * m->p.n_classes * kBlockVoxels * sizeof(uint16_t),
+                            hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    return n;
+}
+
+extern "C" int map_read_block(map_t *m, int32_t bx, int32_t by, int32_t bz, float *D, float *W, uint8_t *fused,
+                              uint16_t *counts)
+{
+    if (!m || read_counters(m)) return 0;
+    const int64_t n = m->h_ctr->pool_used;
+    std::vector<int4> c(n > 0 ? n : 1);
+    if (n > 0 && hipMemcpy(c.data(), m->v.coords, n * sizeof(int4), hipMemcpyDeviceToHost) != hipSuccess) return 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (c[i].x != bx || c[i].y != by || c[i].z != bz) continue;
+        if (D || W) {
+            float2 tmp[kBlockVoxels];
+            if (hipMemcpy(tmp, m->v.dw + i * kBlockVoxels, sizeof(tmp), hipMemcpyDeviceToHost) != hipSuccess) return 0;
+            for (int j = 0; j < kBlockVoxels; ++j) {
+                if (D) D[j] = tmp[j].x;
+                if (W) W[j] = tmp[j].y;
+            }
+        }
+        if (fused && hipMemcpy(fused, m->v.fused + i * kBlockVoxels, kBlockVoxels, hipMemcpyDeviceToHost) != hipSuccess)
+            return 0;
+        const size_t cb = (size_t)m->p.n_classes * kBlockVoxels;
+        if (counts && hipMemcpy(counts, m->v.counts + i * cb, cb * sizeof(uint16_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return 0;
+        return 1;
+    }
+    return 0;
+}

@@ -1,0 +1,329 @@
+"""ctypes binding of the mapcore C ABI (argument marshalling only).
+
+Function names mirror the C entry points.  Device buffers are torch CUDA tensors (HIP
+on ROCm); the stream defaults to torch's current stream.  The binding never computes
+anything itself and raises if ``libmapcore.so`` is absent: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_FILE = os.path.join(_HERE, "libmapcore.so")
+
+MAP_OK, MAP_ERR_INVALID_ARG, MAP_ERR_CAPACITY = 0, -1, -2
+MAP_ERR_BUFFER_TOO_SMALL, MAP_ERR_NO_SCAN, MAP_ERR_DEVICE = -3, -4, -5
+MAP_MESH_DIRTY, MAP_MESH_ALL = 0, 1
+
+
+def lib_path() -> str:
+    return _LIB_FILE
+
+
+if not os.path.exists(_LIB_FILE):
+    raise ImportError(f"mapcore HIP library not built: {_LIB_FILE} is missing "
+                      "(run `python -c 'import __graft_entry__ as g; g.build()'` from the repo root)")
+
+_lib = ctypes.CDLL(_LIB_FILE)
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("truncation", ctypes.c_float),
+                ("max_blocks", ctypes.c_int64), ("n_classes", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class _Lidar(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("elev_rad", ctypes.c_void_p), ("r_max", ctypes.c_float)]
+
+
+class _Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("touched", "new_blocks", "updates", "votes", "mesh_blocks",
+                                              "triangles", "allocated", "frames")]
+
+
+_P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+_sig = {
+    "map_create": (ctypes.c_int, [ctypes.POINTER(_Params), _P, ctypes.POINTER(_P)]),
+    "map_destroy": (None, [_P]),
+    "map_integrate_lidar": (ctypes.c_int, [_P, ctypes.POINTER(_Lidar), _P, _P, _P]),
+    "map_integrate_labels": (ctypes.c_int, [_P, ctypes.POINTER(_Camera), _P, _P, _P]),
+    "map_extract_mesh": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
+    "map_query_sdf": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    "map_sdf_pose_adjoint": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
+    "map_sync": (ctypes.c_int, [_P]),
+    "map_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
+    "map_last_error": (ctypes.c_char_p, [_P]),
+    "map_block_coords": (_I64, [_P, _P, _I64]),
+    "map_touched_coords": (_I64, [_P, _P, _I64]),
+    "map_download": (_I64, [_P, _I64, _P, _P, _P, _P, _P]),
+    "map_read_block": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class MapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mapcore error {code}: {msg}")
+        self.code = code
+
+
+@dataclass
+class LidarModel:
+    rows: int
+    cols: int
+    elev_rad: np.ndarray  # host float32 [rows], top row first
+    r_max: float
+
+    def _c(self):
+        e = np.ascontiguousarray(self.elev_rad, dtype=np.float32)
+        s = _Lidar(self.rows, self.cols, e.ctypes.data, self.r_max)
+        s._keep = e
+        return s
+
+
+@dataclass
+class CameraModel:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    def _c(self):
+        return _Camera(self.width, self.height, self.fx, self.fy, self.cx, self.cy)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name, shape_last=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and t.shape[-1] != shape_last:
+        raise ValueError(f"{name}: last dimension must be {shape_last}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _pose(T):
+    a = np.ascontiguousarray(np.asarray(T, dtype=np.float32).reshape(16))
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+# ----------------------------------------------------------------------------------------
+# functions with the C ABI's names
+# ----------------------------------------------------------------------------------------
+
+def map_create(voxel_size, truncation, max_blocks, n_classes, device=0, stream=None):
+    """Returns (status, handle)."""
+    p = _Params(voxel_size, truncation, int(max_blocks), int(n_classes), int(device))
+    h = _P()
+    st = _lib.map_create(ctypes.byref(p), _stream(stream), ctypes.byref(h))
+    return st, h
+
+
+def map_destroy(handle):
+    _lib.map_destroy(handle)
+
+
+def map_integrate_lidar(handle, lidar: LidarModel, range_dev, T_wl, stream=None):
+    import torch
+    L = lidar._c()
+    keep, T = _pose(T_wl)
+    if range_dev.numel() != lidar.rows * lidar.cols:
+        raise ValueError("range image size does not match the LiDAR model")
+    return _lib.map_integrate_lidar(handle, ctypes.byref(L), _dev(range_dev, torch.float32, "range"), T,
+                                    _stream(stream))
+
+
+def map_integrate_labels(handle, cam: CameraModel, labels_dev, T_wc, stream=None):
+    import torch
+    if labels_dev.numel() != cam.width * cam.height:
+        raise ValueError("label image size does not match the camera model")
+    keep, T = _pose(T_wc)
+    return _lib.map_integrate_labels(handle, ctypes.byref(cam._c()), _dev(labels_dev, torch.uint8, "labels"), T,
+                                     _stream(stream))
+
+
+def map_extract_mesh(handle, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=None):
+    """Returns (status, n_tris).  Capacity is taken from pos_dev ([cap, 3, 3] float32)."""
+    import torch
+    cap = 0 if pos_dev is None else pos_dev.shape[0]
+    if lab_dev is not None and lab_dev.shape[0] < cap:
+        raise ValueError("label buffer smaller than the position buffer")
+    if edge_keys_dev is not None and edge_keys_dev.shape[0] < cap:
+        raise ValueError("edge-key buffer smaller than the position buffer")
+    n = _I64(0)
+    st = _lib.map_extract_mesh(handle, int(mode), _dev(pos_dev, torch.float32, "pos") if cap else None,
+                               _dev(lab_dev, torch.uint8, "lab") if cap else None,
+                               _dev(edge_keys_dev, torch.int64, "edge_keys") if cap else None,
+                               cap, ctypes.byref(n), _stream(stream))
+    return st, n.value
+
+
+def map_query_sdf(handle, pts_dev, sdf_dev, grad_dev, valid_dev, stream=None):
+    import torch
+    n = pts_dev.shape[0]
+    if sdf_dev.shape[0] != n or valid_dev.shape[0] != n or (grad_dev is not None and grad_dev.shape[0] != n):
+        raise ValueError("query output sizes differ from the point count")
+    return _lib.map_query_sdf(handle, _dev(pts_dev, torch.float32, "pts", 3), n, _dev(sdf_dev, torch.float32, "sdf"),
+                              _dev(grad_dev, torch.float32, "grad", 3), _dev(valid_dev, torch.uint8, "valid"),
+                              _stream(stream))
+
+
+def map_sdf_pose_adjoint(handle, xi_dev, pts_dev, loss_dev, gxi_dev, gpts_dev=None, stream=None):
+    import torch
+    B, N = pts_dev.shape[0], pts_dev.shape[1]
+    if tuple(xi_dev.shape) != (B, 6) or tuple(loss_dev.shape) != (B,) or tuple(gxi_dev.shape) != (B, 6):
+        raise ValueError("adjoint argument shapes do not match B")
+    if gpts_dev is not None and tuple(gpts_dev.shape) != tuple(pts_dev.shape):
+        raise ValueError("gpts must have the points' shape")
+    return _lib.map_sdf_pose_adjoint(handle, _dev(xi_dev, torch.float32, "xi"), _dev(pts_dev, torch.float32, "pts", 3),
+                                     B, N, _dev(loss_dev, torch.float32, "loss"), _dev(gxi_dev, torch.float32, "gxi"),
+                                     _dev(gpts_dev, torch.float32, "gpts", 3), _stream(stream))
+
+
+def map_sync(handle):
+    return _lib.map_sync(handle)
+
+
+def map_stats(handle):
+    s = _Stats()
+    st = _lib.map_stats(handle, ctypes.byref(s))
+    return st, {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+
+def map_last_error(handle):
+    r = _lib.map_last_error(handle)
+    return r.decode() if r else ""
+
+
+def map_block_coords(handle):
+    n = _lib.map_block_coords(handle, None, 0)
+    out = np.zeros((max(n, 1), 3), np.int32)
+    _lib.map_block_coords(handle, out.ctypes.data, n)
+    return out[:n]
+
+
+def map_touched_coords(handle):
+    n = _lib.map_touched_coords(handle, None, 0)
+    out = np.zeros((max(n, 1), 3), np.int32)
+    _lib.map_touched_coords(handle, out.ctypes.data, n)
+    return out[:n]
+
+
+def map_download(handle, n_classes, with_counts=True):
+    n = _lib.map_download(handle, 0, None, None, None, None, None)
+    k = max(n, 1)
+    coords = np.zeros((k, 3), np.int32)
+    D = np.zeros((k, 512), np.float32)
+    W = np.zeros((k, 512), np.float32)
+    F = np.zeros((k, 512), np.uint8)
+    C = np.zeros((k, n_classes, 512), np.uint16) if with_counts else None
+    _lib.map_download(handle, n, coords.ctypes.data, D.ctypes.data, W.ctypes.data, F.ctypes.data,
+                      C.ctypes.data if with_counts else None)
+    return {"coords": coords[:n], "D": D[:n], "W": W[:n], "fused": F[:n],
+            "counts": C[:n] if with_counts else None}
+
+
+def map_read_block(handle, b, n_classes):
+    D = np.zeros(512, np.float32)
+    W = np.zeros(512, np.float32)
+    F = np.zeros(512, np.uint8)
+    C = np.zeros((n_classes, 512), np.uint16)
+    ok = _lib.map_read_block(handle, int(b[0]), int(b[1]), int(b[2]), D.ctypes.data, W.ctypes.data,
+                             F.ctypes.data, C.ctypes.data)
+    return {"D": D, "W": W, "fused": F, "counts": C} if ok else None
+
+
+# ----------------------------------------------------------------------------------------
+# convenience wrapper
+# ----------------------------------------------------------------------------------------
+
+class Map:
+    """One map on one device; raises MapError on a non-OK status."""
+
+    def __init__(self, voxel_size, truncation, n_classes, max_blocks, device=0, stream=None):
+        st, h = map_create(voxel_size, truncation, max_blocks, n_classes, device, stream)
+        if st != MAP_OK:
+            raise MapError(st, map_last_error(None))
+        self.h = h
+        self.n_classes = int(n_classes)
+        self.voxel_size, self.truncation = float(voxel_size), float(truncation)
+
+    def _check(self, st, ok=(MAP_OK,)):
+        if st not in ok:
+            raise MapError(st, map_last_error(self.h))
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            map_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate_lidar(self, lidar, range_dev, T_wl, stream=None):
+        return self._check(map_integrate_lidar(self.h, lidar, range_dev, T_wl, stream))
+
+    def integrate_labels(self, cam, labels_dev, T_wc, stream=None):
+        return self._check(map_integrate_labels(self.h, cam, labels_dev, T_wc, stream))
+
+    def extract_mesh(self, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=None, allow_small=False):
+        st, n = map_extract_mesh(self.h, mode, pos_dev, lab_dev, edge_keys_dev, stream)
+        self._check(st, (MAP_OK, MAP_ERR_BUFFER_TOO_SMALL) if allow_small else (MAP_OK,))
+        return st, n
+
+    def query_sdf(self, pts_dev, sdf_dev, grad_dev, valid_dev, stream=None):
+        return self._check(map_query_sdf(self.h, pts_dev, sdf_dev, grad_dev, valid_dev, stream))
+
+    def sdf_pose_adjoint(self, xi_dev, pts_dev, loss_dev, gxi_dev, gpts_dev=None, stream=None):
+        return self._check(map_sdf_pose_adjoint(self.h, xi_dev, pts_dev, loss_dev, gxi_dev, gpts_dev, stream))
+
+    def sync(self):
+        return map_sync(self.h)
+
+    def stats(self):
+        st, s = map_stats(self.h)
+        return st, s
+
+    def block_coords(self):
+        return map_block_coords(self.h)
+
+    def touched_coords(self):
+        return map_touched_coords(self.h)
+
+    def download(self, with_counts=True):
+        return map_download(self.h, self.n_classes, with_counts)
+
+    def read_block(self, b):
+        return map_read_block(self.h, b, self.n_classes)

@@ -1,0 +1,351 @@
+"""GPU parity of the mapping path against the CPU oracle, through the C ABI.
+
+Bar: block sets, label counts and fused labels bit-exact; D and W within 1e-5 relative
+(D on the truncation scale); mesh triangles equal as multisets of edge keys and labels
+with vertices within 1e-4 voxel.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import camera_model, compare_mesh, compare_state, gpu_mesh, lidar_model
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2412_00291_amd  # noqa: F401
+    return torch, torch.device("cuda:0")
+
+
+def _pair(w, max_blocks=None):
+    from paper_2412_00291_amd import Map
+    mb = max_blocks or w.max_blocks
+    return Map(w.voxel, w.trunc, w.n_classes, mb), oracle.OracleMap(w.voxel, w.trunc, w.n_classes, mb)
+
+
+def _step(torch, m, om, w, f, labels=True):
+    dev = torch.device("cuda:0")
+    m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
+    st = om.integrate_lidar(w.lidar, f.range, f.T_wl)
+    if labels:
+        for T, lab, cam in f.cams:
+            m.integrate_labels(camera_model(cam), torch.from_numpy(np.ascontiguousarray(lab)).to(dev), T)
+            om.integrate_labels(cam, lab, T)
+    return st
+
+
+def test_tiny_frame(torch_dev):
+    torch, dev = torch_dev
+    w = synth.tiny_workload()
+    f = w.frame(0)
+    m, om = _pair(w)
+    _step(torch, m, om, w, f)
+    assert m.sync() == 0
+    assert {tuple(b) for b in m.touched_coords()} == {tuple(b) for b in om.touched()}
+    rep = compare_state(m, om)
+    assert rep["blocks"] > 500
+    st, s = m.stats()
+    os_ = om.stats()
+    for k in ("touched", "new_blocks", "updates", "votes", "allocated"):
+        assert s[k] == os_[k], k
+    gm = gpu_mesh(m, 0)
+    st_, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
+    mr = compare_mesh(gm, (pos, lab, keys), voxel=w.voxel)
+    assert mr["triangles"] > 1000
+    st, s = m.stats()
+    assert s["mesh_blocks"] == om.stats()["mesh_blocks"] and s["triangles"] == n
+    # dirty set cleared by the extraction
+    gm2 = gpu_mesh(m, 0)
+    assert gm2["n"] == 0
+
+
+def test_sphere_closed_form_and_three_views(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import Map
+    lidar = synth.uniform_lidar(64, 1800, 60.0, -60.0, 40.0)
+    m = Map(0.2, 0.6, 4, 1 << 16)
+    om = oracle.OracleMap(0.2, 0.6, 4, 1 << 16)
+    rx = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], float)
+    ry = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], float)
+    rimg = synth.constant_range(lidar, 3.0)
+    for Rm in (np.eye(3), rx, ry):
+        T = synth.pose_matrix(Rm, [0.0, 0.0, 0.0])
+        m.integrate_lidar(lidar_model(lidar), torch.from_numpy(rimg).to(dev), T)
+        om.integrate_lidar(lidar, rimg, T)
+    compare_state(m, om)
+    gm = gpu_mesh(m, 1)
+    st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_ALL)
+    compare_mesh(gm, (pos, lab, keys), voxel=0.2)
+
+
+def test_street_window(torch_dev):
+    """Three consecutive 64x2048 frames with four 1280x720 label images each; state and
+    per-frame dirty meshes compared after every frame."""
+    torch, dev = torch_dev
+    w = synth.street_workload(n_frames=3)
+    m, om = _pair(w)
+    for k in range(3):
+        f = w.frame(k)
+        _step(torch, m, om, w, f)
+        rep = compare_state(m, om)
+        gm = gpu_mesh(m, 0)
+        st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
+        compare_mesh(gm, (pos, lab, keys), voxel=w.voxel)
+        st_, s = m.stats()
+        o = om.stats()
+        for key in ("touched", "new_blocks", "updates", "votes", "allocated", "mesh_blocks", "triangles"):
+            assert s[key] == o[key], (k, key, s[key], o[key])
+    assert rep["blocks"] > 5000
+
+
+def test_full_size_128_beam_frame(torch_dev):
+    """One 128x2048 frame (largest LiDAR image), two 1920x1080 label images."""
+    torch, dev = torch_dev
+    w = synth.campus_workload(n_frames=1)
+    w.max_blocks = 1 << 18
+    m, om = _pair(w)
+    f = w.frame(0)
+    _step(torch, m, om, w, f)
+    compare_state(m, om)
+
+
+def test_empty_scan_and_labels(torch_dev):
+    torch, dev = torch_dev
+    w = synth.tiny_workload()
+    m, om = _pair(w)
+    from paper_2412_00291_amd import MAP_ERR_NO_SCAN, map_integrate_labels
+    cam = w.cameras[0]
+    lab = torch.zeros((cam.height, cam.width), dtype=torch.uint8, device=dev)
+    T = synth.pose_matrix(np.eye(3), [0, 0, 0])
+    assert map_integrate_labels(m.h, camera_model(cam), lab, T) == MAP_ERR_NO_SCAN
+    zero = torch.zeros((w.lidar.rows, w.lidar.cols), dtype=torch.float32, device=dev)
+    m.integrate_lidar(lidar_model(w.lidar), zero, T)
+    nan = torch.full((w.lidar.rows, w.lidar.cols), float("nan"), dtype=torch.float32, device=dev)
+    m.integrate_lidar(lidar_model(w.lidar), nan, T)
+    m.integrate_labels(camera_model(cam), lab, T)
+    st, s = m.stats()
+    assert st == 0 and s["allocated"] == 0 and s["updates"] == 0 and s["votes"] == 0
+    assert gpu_mesh(m, 0)["n"] == 0
+
+
+def test_capacity_rejects_frame(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import MAP_ERR_CAPACITY
+    w = synth.tiny_workload()
+    f = w.frame(0)
+    m, om = _pair(w, max_blocks=100)
+    _step(torch, m, om, w, f)
+    assert m.sync() == MAP_ERR_CAPACITY
+    assert m.sync() == 0  # the deferred status is reported once
+    st, s = m.stats()
+    assert s["allocated"] == 0 and s["votes"] == 0 and s["frames"] == 0
+    assert om.num_blocks() == 0
+    assert gpu_mesh(m, 0)["n"] == 0
+
+
+def test_buffer_too_small_keeps_dirty_set(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import MAP_ERR_BUFFER_TOO_SMALL
+    w = synth.tiny_workload()
+    m, om = _pair(w)
+    _step(torch, m, om, w, w.frame(0))
+    small = gpu_mesh(m, 0, cap=16)
+    assert small["status"] == MAP_ERR_BUFFER_TOO_SMALL and small["n"] > 16
+    full = gpu_mesh(m, 0)
+    assert full["status"] == 0 and full["n"] == small["n"]
+    st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
+    compare_mesh(full, (pos, lab, keys), voxel=w.voxel)
+
+
+def test_two_runs_bit_identical(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import Map
+    w = synth.street_workload(n_frames=2)
+    frames = [w.frame(k) for k in range(2)]
+    outs = []
+    for _ in range(2):
+        m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+        for f in frames:
+            m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
+            for T, lab, cam in f.cams:
+                m.integrate_labels(camera_model(cam), torch.from_numpy(np.ascontiguousarray(lab)).to(dev), T)
+        d = m.download()
+        order = np.lexsort(d["coords"].T[::-1])
+        mesh = gpu_mesh(m, 1)
+        tri = sorted(zip(map(tuple, mesh["keys"].tolist()), mesh["pos"].reshape(len(mesh["keys"]), 9).tolist()))
+        outs.append(({k: v[order] for k, v in d.items()}, tri))
+        m.close()
+    for k in ("coords", "D", "W", "fused", "counts"):
+        assert np.array_equal(outs[0][0][k].view(np.uint8), outs[1][0][k].view(np.uint8)), k
+    assert outs[0][1] == outs[1][1]
+
+
+def _tri_blocks(keys):
+    """Block of the cube that produced each triangle: the cube's lower corner is the
+    component-wise minimum of its edges' base voxels (no triangle lies on one face)."""
+    off = 1 << 19
+    v = np.stack([(keys >> 42) & 0xFFFFF, (keys >> 22) & 0xFFFFF, (keys >> 2) & 0xFFFFF], -1) - off
+    return np.floor_divide(v.min(axis=1), 8)
+
+
+def test_incremental_union_equals_full_remesh(torch_dev):
+    """Meshing the dirty blocks after frames 0, 2 and 3 (frame 1's blocks wait for the
+    next extraction) and keeping each block's latest mesh equals meshing everything."""
+    torch, dev = torch_dev
+    from collections import Counter
+    from tests.gpu_helpers import step_log
+    w = synth.street_workload(n_frames=4)
+    m, _ = _pair(w)
+    acc = {}
+    pending = set()
+    for k in range(4):
+        f = w.frame(k, with_labels=False)
+        m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
+        step_log(f"incremental: frame {k} enqueued")
+        allocated = {tuple(b) for b in m.block_coords()}
+        for b in m.touched_coords():
+            for e in range(8):
+                nb = (b[0] - (e & 1), b[1] - ((e >> 1) & 1), b[2] - ((e >> 2) & 1))
+                if nb in allocated:
+                    pending.add(nb)
+        step_log(f"incremental: frame {k} dirty set {len(pending)}")
+        if k == 1:
+            continue
+        gm = gpu_mesh(m, 0)
+        step_log(f"incremental: frame {k} meshed {gm['n']} triangles")
+        st, s = m.stats()
+        assert s["mesh_blocks"] == len(pending)
+        blk = _tri_blocks(gm["keys"])
+        for b in pending:
+            acc[b] = []
+        for t, b in enumerate(map(tuple, blk.tolist())):
+            assert b in pending
+            acc[b].append((tuple(gm["keys"][t].tolist()), tuple(gm["lab"][t].tolist()), gm["pos"][t].tobytes()))
+        pending = set()
+    full = gpu_mesh(m, 1)
+    want = Counter(zip(map(tuple, full["keys"].tolist()), map(tuple, full["lab"].tolist()),
+                       [p.tobytes() for p in full["pos"]]))
+    got = Counter(x for v in acc.values() for x in v)
+    assert got == want and full["n"] > 100000
+    m.close()
+
+
+def test_query_parity(torch_dev):
+    torch, dev = torch_dev
+    w = synth.tiny_workload()
+    m, om = _pair(w)
+    f = w.frame(0, with_labels=False)
+    _step(torch, m, om, w, f, labels=False)
+    rng = np.random.Generator(np.random.PCG64(12))
+    pts = synth.scan_points(w, synth.uniform_lidar(64, 2048, 15.0, -15.0, 40.0), f.T_wl, 131072, seed=3)
+    pts = (pts + rng.normal(0, 0.1, size=pts.shape)).astype(np.float32)
+    pts = np.concatenate([pts, rng.uniform(-50, 50, size=(4096, 3)).astype(np.float32)])
+    n = len(pts)
+    P = torch.from_numpy(pts).to(dev)
+    sdf = torch.empty(n, device=dev)
+    grad = torch.empty(n, 3, device=dev)
+    valid = torch.empty(n, dtype=torch.uint8, device=dev)
+    m.query_sdf(P, sdf, grad, valid)
+    osdf, ograd, ovalid = om.query_sdf(pts.astype(np.float64), mode=1)
+    gv = valid.cpu().numpy().astype(bool)
+    assert np.array_equal(gv, ovalid) and ovalid.sum() > 10000
+    tau = np.float32(w.trunc)
+    assert np.all(np.abs(sdf.cpu().numpy()[gv] - osdf[gv]) <= 1e-5 * tau)
+    g = grad.cpu().numpy()[gv]
+    assert np.all(np.abs(g - ograd[gv]) <= 1e-5 * np.maximum(np.abs(ograd[gv]), tau / w.voxel))
+
+
+def test_pose_adjoint_full_size(torch_dev):
+    """64 poses x 131072 points (the differentiation workload) on the GPU; 4 poses checked
+    against the fp64 oracle and fp64 central differences of the oracle loss."""
+    torch, dev = torch_dev
+    w = synth.tiny_workload()
+    m, om = _pair(w)
+    f = w.frame(0, with_labels=False)
+    _step(torch, m, om, w, f, labels=False)
+    pts = synth.scan_points(w, synth.uniform_lidar(64, 2048, 15.0, -15.0, 40.0), f.T_wl, 131072, seed=4)
+    xi = synth.perturbed_poses(64, seed=4)
+    B, N = 64, 131072
+    P = torch.from_numpy(np.broadcast_to(pts, (B, N, 3)).copy()).to(dev)
+    X = torch.from_numpy(xi).to(dev)
+    loss = torch.empty(B, device=dev)
+    gxi = torch.empty(B, 6, device=dev)
+    gp = torch.empty_like(P)
+    m.sdf_pose_adjoint(X, P, loss, gxi, gp)
+    loss2 = torch.empty(B, device=dev)
+    gxi2 = torch.empty(B, 6, device=dev)
+    m.sdf_pose_adjoint(X, P, loss2, gxi2, None)
+    assert torch.equal(loss, loss2) and torch.equal(gxi, gxi2)  # fixed-order reduction
+    L, G, GP = loss.cpu().numpy(), gxi.cpu().numpy(), gp.cpu().numpy()
+    for b in (0, 17, 40, 63):
+        ol, og, ogp, margin = om.pose_adjoint(xi[b:b + 1].astype(np.float64), pts[None])
+        g_norm = np.linalg.norm(ogp[0], axis=1)
+        scale_t = g_norm.sum()
+        scale_w = (np.linalg.norm(pts, axis=1) * g_norm).sum()
+        assert abs(L[b] - ol[0]) <= 1e-4 * ol[0] + 1e-3 * w.trunc ** 2, (b, L[b], ol[0])
+        assert np.all(np.abs(G[b, :3] - og[0, :3]) <= 1e-4 * scale_t + 1e-3), (b, G[b], og[0])
+        assert np.all(np.abs(G[b, 3:] - og[0, 3:]) <= 1e-4 * scale_w + 1e-3), (b, G[b], og[0])
+        # per point: away from cell faces (where the fp32 and fp64 cell choice can differ
+        # and the trilinear gradient jumps) the error is bounded relative to the term's
+        # natural scale 2 tau |grad D| + |g| (D itself is near zero at the surface)
+        from scipy.spatial.transform import Rotation
+        y = Rotation.from_rotvec(xi[b, 3:].astype(np.float64)).apply(pts.astype(np.float64)) + xi[b, :3]
+        _, ograd, ovalid = om.query_sdf(y, mode=0)
+        safe = (margin[0] > 1e-3) & ovalid
+        err = np.abs(GP[b][safe] - ogp[0][safe]).max(axis=1)
+        scale = 2 * w.trunc * np.linalg.norm(ograd[safe], axis=1) + g_norm[safe]
+        assert np.all(err <= 1e-4 * scale + 1e-7), (b, (err / (scale + 1e-30)).max())
+    # fp64 central differences (step 1e-4) of the oracle loss, over the points whose
+    # validity is the same at every stencil pose (the loss jumps where it changes), against
+    # the GPU adjoint of the same points
+    from scipy.spatial.transform import Rotation
+    h = 1e-4
+    for b in (0, 40):
+        x0 = xi[b].astype(np.float64)
+        stencil = [x0] + [x0 + s * h * np.eye(6)[i] for i in range(6) for s in (-1, 1)]
+        valid = []
+        for xs in stencil:
+            y = Rotation.from_rotvec(xs[3:]).apply(pts.astype(np.float64)) + xs[:3]
+            valid.append(om.query_sdf(y, mode=0)[2])
+        keep = np.all(np.stack(valid) == valid[0], axis=0)
+        sub = np.ascontiguousarray(pts[keep])
+        assert keep.mean() > 0.99
+        Ps = torch.from_numpy(sub[None]).to(dev)
+        ls, gs = torch.empty(1, device=dev), torch.empty(1, 6, device=dev)
+        m.sdf_pose_adjoint(torch.from_numpy(xi[b:b + 1]).to(dev), Ps, ls, gs, None)
+        gs = gs.cpu().numpy()[0]
+        _, og, ogp, _ = om.pose_adjoint(x0[None], sub[None])
+        g_norm = np.linalg.norm(ogp[0], axis=1)
+        scales = [g_norm.sum()] * 3 + [(np.linalg.norm(sub, axis=1) * g_norm).sum()] * 3
+        for i in range(6):
+            lp = om.pose_adjoint(stencil[2 + 2 * i][None], sub[None])[0][0]
+            lm = om.pose_adjoint(stencil[1 + 2 * i][None], sub[None])[0][0]
+            fd = (lp - lm) / (2 * h)
+            assert abs(gs[i] - fd) <= 1e-3 * scales[i], (b, i, gs[i], fd, scales[i])
+
+
+def test_autograd_function(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd.autograd import sdf_pose_loss
+    w = synth.tiny_workload()
+    m, om = _pair(w)
+    f = w.frame(0, with_labels=False)
+    _step(torch, m, om, w, f, labels=False)
+    pts = synth.scan_points(w, synth.uniform_lidar(16, 1024, 15.0, -15.0, 40.0), f.T_wl, 16 * 1024, seed=5)
+    xi = torch.from_numpy(synth.perturbed_poses(4, seed=5)).to(dev).requires_grad_(True)
+    P = torch.from_numpy(np.broadcast_to(pts, (4, len(pts), 3)).copy()).to(dev).requires_grad_(True)
+    loss = sdf_pose_loss(m, xi, P)
+    wts = torch.tensor([1.0, 2.0, 0.5, -1.0], device=dev)
+    (loss * wts).sum().backward()
+    l2 = torch.empty(4, device=dev)
+    g2 = torch.empty(4, 6, device=dev)
+    gp2 = torch.empty_like(P)
+    m.sdf_pose_adjoint(xi.detach(), P.detach(), l2, g2, gp2)
+    assert torch.equal(loss.detach(), l2)
+    torch.testing.assert_close(xi.grad, wts[:, None] * g2)
+    torch.testing.assert_close(P.grad, wts[:, None, None] * gp2)
