@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-frame mapping path on one MI355X.
+
+Workload: the 64-beam street sequence (64x2048 range images, +2/-24.8 deg, 100 m, four
+1280x720 label cameras with 19 classes, 0.1 m voxels, 0.3 m truncation, 10 Hz at 1 m/s),
+synthetic and seeded.  One step = one frame of the whole path: block allocation + TSDF
+integration of the scan, label fusion of the four images, and marching cubes of the dirty
+blocks (the triangle count is read back, as a caller must).  Inputs are uploaded to HBM
+before the timed region.
+
+Printed (one JSON line): voxel-updates/s over the timed frames (U_k from an untimed
+counting pass of the same frames), ms per frame, per-kernel averages from HIP events on
+the launch stream, the HBM roofline of the dominant kernel (algorithmic bytes per launch
+over its average duration) and the CPU oracle timed on a bounded sample of the same
+frames on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+METRIC = "voxel-updates/s and ms/frame (64-beam scan, 0.1 m voxels) vs oracle"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_frames(w, n, with_labels=True):
+    frames = []
+    t0 = time.time()
+    for k in range(n):
+        frames.append(w.frame(k, with_labels=with_labels))
+        if (k + 1) % 10 == 0:
+            log(f"[bench] generated {k + 1}/{n} frames ({time.time() - t0:.1f} s)")
+    return frames
+
+
+def run_frames(torch, m, w, dev_frames, lidar, cams, ks, pos, lab, stats=False, step_times=None):
+    from paper_2412_00291_amd import MAP_MESH_DIRTY
+    out = []
+    for k in ks:
+        rng_d, labs_d, T, Tcs = dev_frames[k]
+        t0 = time.perf_counter()
+        m.integrate_lidar(lidar, rng_d, T)
+        for c, (cam, Tc) in enumerate(zip(cams, Tcs)):
+            m.integrate_labels(cam, labs_d[c], Tc)
+        st, n = m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+        if step_times is not None:
+            step_times.append(time.perf_counter() - t0)
+        if stats:
+            st2, s = m.stats()
+            out.append(s)
+    return out
+
+
+def algorithmic_bytes(kernel, s, rows, cols, cams):
+    """Bytes the method must move per frame for one kernel (the HBM-roofline model)."""
+    U, V, T, M, Tri = s["updates"], s["votes"], s["touched"], s["mesh_blocks"], s["triangles"]
+    if kernel == "tsdf":       # read + write (D, W) per update, the range image, the touched list
+        return 16 * U + 4 * rows * cols + 16 * T
+    if kernel == "mesh":       # 9^3 halo of (D, W, fused) per block, 3 x (12 B + 1 B) per triangle
+        return 6561 * M + 39 * Tri
+    if kernel == "labels":     # count r/w, fused r/w, count of the fused label; the label images
+        return 8 * V + sum(c.width * c.height for c in cams)
+    if kernel == "alloc":      # the range image, one probe + list entry per touched block
+        return 4 * rows * cols + 16 * T
+    if kernel == "finish":     # list read, neighbour probes
+        return 16 * T * 8
+    return 0
+
+
+def cpu_baseline(w, frames, budget_s):
+    import oracle
+    om = oracle.OracleMap(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    U = 0
+    t_total = 0.0
+    n = 0
+    for k, f in enumerate(frames):
+        t0 = time.perf_counter()
+        om.integrate_lidar(w.lidar, f.range, f.T_wl)
+        for T, lab, cam in f.cams:
+            om.integrate_labels(cam, lab, T)
+        om.extract_mesh(oracle.MESH_DIRTY, with_keys=False)
+        t_total += time.perf_counter() - t0
+        U += om.stats()["updates"]
+        n += 1
+        if t_total >= budget_s:
+            break
+    return {"value": U / t_total, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"street frames 0-{n - 1} of the same sequence, whole path per frame "
+                      f"(scan + 4 label images + dirty mesh), single-threaded plain C",
+            "ms_per_frame": 1e3 * t_total / n, "frames": n,
+            "cpu": _cpu_model(), "host_threads_available": len(os.sched_getaffinity(0))}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_adjoint(torch, reps=5):
+    """Differentiation workload: 64 poses x 131072 points against the tiny-scene map."""
+    import synth
+    from paper_2412_00291_amd import LidarModel, Map
+    w = synth.tiny_workload()
+    f = w.frame(0, with_labels=False)
+    m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    lidar = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
+    m.integrate_lidar(lidar, torch.from_numpy(f.range).cuda(), f.T_wl)
+    pts = synth.scan_points(w, synth.uniform_lidar(64, 2048, 15.0, -15.0, 40.0), f.T_wl, 131072, seed=4)
+    B, N = 64, 131072
+    P = torch.from_numpy(np.broadcast_to(pts, (B, N, 3)).copy()).cuda()
+    X = torch.from_numpy(synth.perturbed_poses(B, seed=4)).cuda()
+    loss = torch.empty(B, device="cuda")
+    gxi = torch.empty(B, 6, device="cuda")
+    gp = torch.empty_like(P)
+    m.sdf_pose_adjoint(X, P, loss, gxi, gp)
+    torch.cuda.synchronize()
+    m.profile(1 << 6)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m.sdf_pose_adjoint(X, P, loss, gxi, gp)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    prof = m.profile_read()["adjoint"]
+    k_ms = prof[0] / max(prof[1], 1)
+    bytes_ = B * N * (12 + 12) + B * 6 * 4 * 2  # points in, point gradients out, poses
+    m.close()
+    return {"workload": "64 poses x 131072 points, tiny-scene map (0.2 m voxels)",
+            "ms_per_call": 1e3 * dt, "points_per_s": B * N / dt, "kernel_ms": k_ms,
+            "roofline": {"bound": "hbm", "achieved": bytes_ / (k_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": bytes_ / (k_ms * 1e-3) / PEAK_HBM}}
+
+
+def calibrate_copy(torch):
+    """A plain copy of known size, for scaling HBM counters (FETCH_SIZE / WRITE_SIZE)."""
+    n = 256 << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=90)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              "(maps shard by block ownership, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
+    import synth
+    from paper_2412_00291_amd import CameraModel, LidarModel, Map, KERNEL_NAMES
+
+    K, W = args.steps, args.warmup
+    nfr = K + W
+    w = synth.street_workload(n_frames=nfr)
+    log(f"[bench] workload {w.name}: {nfr} frames, {len(w.cameras)} cameras")
+    frames = make_frames(w, nfr)
+    lidar = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
+    cams = [CameraModel(c.width, c.height, c.fx, c.fy, c.cx, c.cy) for c in w.cameras]
+    dev_frames = []
+    for f in frames:
+        labs = torch.from_numpy(np.stack([np.ascontiguousarray(l) for _, l, _ in f.cams])).cuda()
+        dev_frames.append((torch.from_numpy(f.range).cuda(), labs, f.T_wl, [T for T, _, _ in f.cams]))
+    torch.cuda.synchronize()
+    cap = 4_000_000
+    pos = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
+    lab = torch.empty((cap, 3), dtype=torch.uint8, device="cuda")
+
+    # counting pass (untimed): per-frame U_k, V_k, |T_k|, |M_k|, triangles
+    m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    per_frame = run_frames(torch, m, w, dev_frames, lidar, cams, range(nfr), pos, lab, stats=True)
+    m.close()
+    log(f"[bench] counting pass done: frame {W} has U={per_frame[W]['updates']} "
+        f"T={per_frame[W]['touched']} M={per_frame[W]['mesh_blocks']} tris={per_frame[W]['triangles']}")
+
+    # timed pass
+    m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    run_frames(torch, m, w, dev_frames, lidar, cams, range(W), pos, lab)
+    torch.cuda.synchronize()
+    m.profile(0xFF)
+    step_times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_frames(torch, m, w, dev_frames, lidar, cams, range(W, nfr), pos, lab, step_times=step_times)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = m.profile_read()
+    m.close()
+    elapsed = t1 - t0
+    timed = per_frame[W:]
+    U = sum(s["updates"] for s in timed)
+    value = U / elapsed
+
+    kern = {k: {"avg_us": 1e3 * prof[k][0] / prof[k][1], "launches": prof[k][1], "total_ms": prof[k][0]}
+            for k in KERNEL_NAMES if prof[k][1] > 0}
+    dominant = max((k for k in kern if k != "small"), key=lambda k: kern[k]["total_ms"])
+    alg = sum(algorithmic_bytes(dominant, s, w.lidar.rows, w.lidar.cols, w.cameras) for s in timed)
+    launches = kern[dominant]["launches"]
+    achieved = (alg / launches) / (kern[dominant]["avg_us"] * 1e-6)
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
+                "alg_bytes_per_launch": alg / launches}
+    integ_ms = sum(kern[k]["total_ms"] for k in ("alloc", "tsdf", "finish", "labels") if k in kern)
+    mesh_ms = kern.get("mesh", {"total_ms": float("nan")})["total_ms"]
+    st = np.array(step_times) * 1e3
+    result = {
+        "metric": METRIC, "value": value, "unit": "voxel-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": 1e3 * elapsed / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name + "-tau0.3-4cam-1280x720-L19", "frames_timed": K,
+                   "scan": "64x2048 +2/-24.8 deg, 100 m", "voxel_m": w.voxel, "truncation_m": w.trunc,
+                   "cameras": "4 x 1280x720, 19 classes", "meshing": "dirty blocks every frame"},
+        "ms_per_frame_p50": float(np.median(st)), "ms_per_frame_p90": float(np.percentile(st, 90)),
+        "integration_updates_per_s": U / (integ_ms * 1e-3),
+        "mesh_blocks_per_s": sum(s["mesh_blocks"] for s in timed) / (mesh_ms * 1e-3),
+        "per_frame_means": {k: float(np.mean([s[k] for s in timed])) for k in
+                            ("updates", "votes", "touched", "new_blocks", "mesh_blocks", "triangles")},
+        "kernels": kern,
+        "roofline": roofline,
+    }
+    if not args.no_extensions:
+        result["extensions"] = {"pose_adjoint": bench_adjoint(torch)}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_baseline_seconds)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,22 @@ int map_stats(map_t *map, map_frame_stats *out);
  * failure of map_create. */
 const char *map_last_error(const map_t *map);
 
+/* Kernel timing with HIP events recorded on the launch stream around each launch of the
+ * kernels selected by `mask` (bit i = kernel id i below; 0 disables).  map_profile_read
+ * synchronises, writes per-kernel totals (ms) and launch counts since the last read into
+ * arrays of MAP_KERNEL_COUNT entries, and clears them. */
+#define MAP_K_ALLOC 0      /* band-segment walk, frame set, touched list */
+#define MAP_K_TSDF 1       /* block commit + projective TSDF update */
+#define MAP_K_FINISH 2     /* dirty marking, frame-set clear */
+#define MAP_K_LABELS 3     /* label vote fusion (one launch per camera) */
+#define MAP_K_MESH 4       /* marching cubes */
+#define MAP_K_QUERY 5      /* trilinear SDF query */
+#define MAP_K_ADJOINT 6    /* pose / point adjoint (both of its launches) */
+#define MAP_K_SMALL 7      /* single-thread bookkeeping launches */
+#define MAP_KERNEL_COUNT 8
+int map_profile(map_t *map, uint32_t mask);
+int map_profile_read(map_t *map, double *total_ms, int64_t *launches);
+
 /* Test and benchmark access (synchronous): copy the coordinates [n][3] int32 of all
  * allocated blocks in slot order, or the touched blocks of the last frame; returns the
  * count (entries beyond cap are not written). */

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -34,6 +35,12 @@ struct map_s {
     // adjoint partial sums
     float *partial = nullptr;
     size_t partial_floats = 0;
+    // kernel timing: pending (kernel id, start, stop) event triples and a free list
+    uint32_t prof_mask = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+    std::vector<hipEvent_t> prof_free;
+    double prof_ms[MAP_KERNEL_COUNT] = {};
+    int64_t prof_n[MAP_KERNEL_COUNT] = {};
 };
 
 static std::string g_create_error;
@@ -67,6 +74,13 @@ static uint64_t next_pow2(uint64_t x)
 
 static void free_all(map_t *m)
 {
+    for (auto &p : m->prof_pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : m->prof_free) (void)hipEventDestroy(e);
+    m->prof_pending.clear();
+    m->prof_free.clear();
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.dirty_flag,
                     m->v.dirty_list, m->v.ctr, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->lut_buf, m->partial};
@@ -91,6 +105,65 @@ static bool pose_ok(const float *T)
                  (double)T[1] * ((double)T[4] * T[10] - (double)T[6] * T[8]) +
                  (double)T[2] * ((double)T[4] * T[9] - (double)T[5] * T[8]);
     return det > 0.0;
+}
+
+static hipEvent_t take_event(map_t *m)
+{
+    if (!m->prof_free.empty()) {
+        hipEvent_t e = m->prof_free.back();
+        m->prof_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch through `fn`, bracketed by events on the same stream when kernel `kid` is timed.
+template <class F>
+static hipError_t timed(map_t *m, int kid, hipStream_t s, F fn)
+{
+    if (!((m->prof_mask >> kid) & 1u)) return fn();
+    hipEvent_t a = take_event(m), b = take_event(m);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    m->prof_pending.push_back({kid, {a, b}});
+    return hipSuccess;
+}
+
+extern "C" int map_profile(map_t *m, uint32_t mask)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    m->prof_mask = mask & ((1u << MAP_KERNEL_COUNT) - 1);
+    return MAP_OK;
+}
+
+extern "C" int map_profile_read(map_t *m, double *total_ms, int64_t *launches)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    for (auto &p : m->prof_pending) {
+        HIP_TRY(m, hipEventSynchronize(p.second.second));
+        float ms = 0.0f;
+        HIP_TRY(m, hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        m->prof_ms[p.first] += ms;
+        m->prof_n[p.first] += 1;
+        m->prof_free.push_back(p.second.first);
+        m->prof_free.push_back(p.second.second);
+    }
+    m->prof_pending.clear();
+    for (int k = 0; k < MAP_KERNEL_COUNT; ++k) {
+        if (total_ms) total_ms[k] = m->prof_ms[k];
+        if (launches) launches[k] = m->prof_n[k];
+        m->prof_ms[k] = 0.0;
+        m->prof_n[k] = 0;
+    }
+    return MAP_OK;
 }
 
 static Pose to_pose(const float *T)
@@ -310,10 +383,12 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     rc = ensure_frame_scratch(m, L, s);
     if (rc) return rc;
     const Pose T = to_pose(T_wl);
-    HIP_TRY(m, launch_frame_begin(m->v, s));
-    HIP_TRY(m, launch_alloc(m->v, m->f, m->lut, T, range_dev, s));
-    HIP_TRY(m, launch_tsdf(m->v, m->f, m->lut, T, range_dev, grid_for(m->f.tk_cap, 1, 2048), s));
-    HIP_TRY(m, launch_finish(m->v, m->f, grid_for(m->f.tk_cap, 256, 1024), s));
+    HIP_TRY(m, timed(m, MAP_K_SMALL, s, [&] { return launch_frame_begin(m->v, s); }));
+    HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] { return launch_alloc(m->v, m->f, m->lut, T, range_dev, s); }));
+    HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
+        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, grid_for(m->f.tk_cap, 1, 2048), s);
+    }));
+    HIP_TRY(m, timed(m, MAP_K_FINISH, s, [&] { return launch_finish(m->v, m->f, grid_for(m->f.tk_cap, 256, 1024), s); }));
     m->last_stream = s;
     m->has_scan = true;
     return MAP_OK;
@@ -332,7 +407,10 @@ extern "C" int map_integrate_labels(map_t *m, const camera_model *cam, const uin
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
     Camera c{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
-    HIP_TRY(m, launch_labels(m->v, m->f, c, to_pose(T_wc), labels_dev, grid_for(m->f.tk_cap, 1, 2048), s));
+    const Pose T = to_pose(T_wc);
+    HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
+        return launch_labels(m->v, m->f, c, T, labels_dev, grid_for(m->f.tk_cap, 1, 2048), s);
+    }));
     m->last_stream = s;
     return MAP_OK;
 }
@@ -347,8 +425,8 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
-    HIP_TRY(m, launch_mesh_begin(m->v, s));
-    HIP_TRY(m, launch_mesh(m->v, mode, out, grid_for(m->p.max_blocks, 1, 2048), s));
+    HIP_TRY(m, timed(m, MAP_K_SMALL, s, [&] { return launch_mesh_begin(m->v, s); }));
+    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] { return launch_mesh(m->v, mode, out, grid_for(m->p.max_blocks, 1, 2048), s); }));
     HIP_TRY(m, hipMemcpyAsync(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(m, hipStreamSynchronize(s));
     m->last_stream = s;
@@ -357,7 +435,7 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     if (n > cap_tris)
         return fail(m, MAP_ERR_BUFFER_TOO_SMALL, "extract_mesh: %lld triangles, capacity %lld", (long long)n,
                     (long long)cap_tris);
-    if (mode == MAP_MESH_DIRTY) HIP_TRY(m, launch_mesh_end(m->v, s));
+    if (mode == MAP_MESH_DIRTY) HIP_TRY(m, timed(m, MAP_K_SMALL, s, [&] { return launch_mesh_end(m->v, s); }));
     return MAP_OK;
 }
 
@@ -369,7 +447,7 @@ extern "C" int map_query_sdf(map_t *m, const float *pts_dev, int64_t n, float *s
         return fail(m, MAP_ERR_INVALID_ARG, "query_sdf: bad arguments");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
-    HIP_TRY(m, launch_query(m->v, pts_dev, n, sdf_dev, grad_dev, valid_dev, s));
+    HIP_TRY(m, timed(m, MAP_K_QUERY, s, [&] { return launch_query(m->v, pts_dev, n, sdf_dev, grad_dev, valid_dev, s); }));
     m->last_stream = s;
     return MAP_OK;
 }
@@ -393,8 +471,10 @@ extern "C" int map_sdf_pose_adjoint(map_t *m, const float *xi_dev, const float *
         HIP_TRY(m, hipMalloc(&m->partial, need * sizeof(float)));
         m->partial_floats = need;
     }
-    HIP_TRY(m, launch_adjoint(m->v, xi_dev, pts_dev, B, N, gpts_dev, m->partial, (int)nchunk, s));
-    HIP_TRY(m, launch_adjoint_reduce(xi_dev, m->partial, B, (int)nchunk, loss_dev, gxi_dev, s));
+    HIP_TRY(m, timed(m, MAP_K_ADJOINT, s, [&] {
+        hipError_t e = launch_adjoint(m->v, xi_dev, pts_dev, B, N, gpts_dev, m->partial, (int)nchunk, s);
+        return e != hipSuccess ? e : launch_adjoint_reduce(xi_dev, m->partial, B, (int)nchunk, loss_dev, gxi_dev, s);
+    }));
     m->last_stream = s;
     return MAP_OK;
 }

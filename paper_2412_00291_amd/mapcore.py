@@ -67,7 +67,11 @@ _sig = {
     "map_touched_coords": (_I64, [_P, _P, _I64]),
     "map_download": (_I64, [_P, _I64, _P, _P, _P, _P, _P]),
     "map_read_block": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "map_profile": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "map_profile_read": (ctypes.c_int, [_P, _P, _P]),
 }
+
+KERNEL_NAMES = ["alloc", "tsdf", "finish", "labels", "mesh", "query", "adjoint", "small"]
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -251,6 +255,20 @@ def map_download(handle, n_classes, with_counts=True):
             "counts": C[:n] if with_counts else None}
 
 
+def map_profile(handle, mask):
+    return _lib.map_profile(handle, int(mask))
+
+
+def map_profile_read(handle):
+    """{kernel name: (total ms, launches)} since the last read (synchronises)."""
+    ms = np.zeros(len(KERNEL_NAMES), np.float64)
+    n = np.zeros(len(KERNEL_NAMES), np.int64)
+    st = _lib.map_profile_read(handle, ms.ctypes.data, n.ctypes.data)
+    if st != MAP_OK:
+        raise MapError(st, map_last_error(handle))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+
 def map_read_block(handle, b, n_classes):
     D = np.zeros(512, np.float32)
     W = np.zeros(512, np.float32)
@@ -324,6 +342,12 @@ class Map:
 
     def download(self, with_counts=True):
         return map_download(self.h, self.n_classes, with_counts)
+
+    def profile(self, mask):
+        return self._check(map_profile(self.h, mask))
+
+    def profile_read(self):
+        return map_profile_read(self.h)
 
     def read_block(self, b):
         return map_read_block(self.h, b, self.n_classes)
