@@ -112,6 +112,11 @@ int map_integrate_lidar(map_t *map, const lidar_model *lidar, const float *range
 int map_integrate_labels(map_t *map, const camera_model *cam, const uint8_t *labels_dev,
                          const float T_wc[16], void *stream);
 
+/* The same for n cameras at once (host arrays: cams [n], labels_dev [n] device pointers,
+ * T_wc [n][16]); the result equals n map_integrate_labels calls in array order. */
+int map_integrate_labels_multi(map_t *map, int32_t n, const camera_model *cams,
+                               const uint8_t *const *labels_dev, const float *T_wc, void *stream);
+
 /* Marching cubes over blocks (end of Sec. IV-C.3): a cube whose eight corner voxels are
  * all observed (W > 0) emits triangles on its edges whose corners differ in D < 0;
  * each vertex lies at the linear zero crossing and carries the most probable label of
@@ -140,6 +145,42 @@ int map_query_sdf(map_t *map, const float *pts_dev, int64_t n, float *sdf_dev, f
 int map_sdf_pose_adjoint(map_t *map, const float *xi_dev, const float *pts_dev, int32_t B,
                          int64_t N, float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream);
 
+/* Batched integration (many maps of uneven size per step).  A batch holds up to 64 maps
+ * created with map_create.  One map_batch_step integrates one frame into each listed map
+ * (LiDAR scan, up to 8 camera label images, then DIRTY meshing into that map's output
+ * buffers) with one launch per phase covering every map, replayed from a captured
+ * hipGraph when enabled.  Each map ends in the state the same sequence of plain calls
+ * (map_integrate_lidar, map_integrate_labels_multi, map_extract_mesh DIRTY) produces.
+ * Items list distinct maps by index; the host pointers in an item are read during the
+ * call.  n_tris [n_items] (host) receives each map's triangle count.  Returns MAP_OK,
+ * MAP_ERR_BUFFER_TOO_SMALL if any map's output was too small (that map keeps its dirty
+ * set), or an argument/device error; capacity rejections are reported per map by
+ * map_sync.  Synchronises `stream`. */
+typedef struct map_batch_s map_batch_t;
+typedef struct {
+    int32_t map_index;
+    const lidar_model *lidar;
+    const float *range_dev;
+    const float *T_wl; /* host [16] */
+    int32_t n_cams;    /* 0..8 */
+    const camera_model *cams;
+    const uint8_t *const *labels_dev;
+    const float *T_wc; /* host [n_cams][16] */
+    float *pos_dev;
+    uint8_t *lab_dev;
+    int64_t *edge_keys_dev; /* nullable */
+    int64_t cap_tris;
+} map_batch_item;
+
+int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out);
+/* schedule: 0 = one workgroup per touched block, 1 = one wavefront per touched block;
+ * grid: workgroups of the persistent phases (64..65536); use_graph: capture each step
+ * shape once in a hipGraph and replay it. */
+int map_batch_configure(map_batch_t *batch, int32_t schedule, int32_t grid, int32_t use_graph);
+int map_batch_step(map_batch_t *batch, const map_batch_item *items, int32_t n_items, int64_t *n_tris,
+                   void *stream);
+void map_batch_destroy(map_batch_t *batch);
+
 /* Synchronise the map's last stream and return (then clear) any deferred status. */
 int map_sync(map_t *map);
 
@@ -155,14 +196,13 @@ const char *map_last_error(const map_t *map);
  * synchronises, writes per-kernel totals (ms) and launch counts since the last read into
  * arrays of MAP_KERNEL_COUNT entries, and clears them. */
 #define MAP_K_ALLOC 0      /* band-segment walk, frame set, touched list */
-#define MAP_K_TSDF 1       /* block commit + projective TSDF update */
-#define MAP_K_FINISH 2     /* dirty marking, frame-set clear */
-#define MAP_K_LABELS 3     /* label vote fusion (one launch per camera) */
-#define MAP_K_MESH 4       /* marching cubes */
-#define MAP_K_QUERY 5      /* trilinear SDF query */
-#define MAP_K_ADJOINT 6    /* pose / point adjoint (both of its launches) */
-#define MAP_K_SMALL 7      /* single-thread bookkeeping launches */
-#define MAP_KERNEL_COUNT 8
+#define MAP_K_TSDF 1       /* block commit, projective TSDF update, dirty marking */
+#define MAP_K_LABELS 2     /* label vote fusion (one launch per up to 8 cameras) */
+#define MAP_K_MESH 3       /* marching cubes */
+#define MAP_K_QUERY 4      /* trilinear SDF query */
+#define MAP_K_ADJOINT 5    /* pose / point adjoint (both of its launches) */
+#define MAP_K_BATCH 6      /* batched multi-map step */
+#define MAP_KERNEL_COUNT 7
 int map_profile(map_t *map, uint32_t mask);
 int map_profile_read(map_t *map, double *total_ms, int64_t *launches);
 

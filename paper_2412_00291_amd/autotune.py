@@ -1,0 +1,71 @@
+"""Autotuner of the batched step's schedule (one workgroup or one wavefront per touched
+block in the TSDF and label phases) and persistent grid size.
+
+Each candidate runs the same frames on freshly created maps (the maps are mutated by a
+step, so candidates never share them); the step times after the first (which also sizes
+the scratch buffers and captures the graph) are compared and the fastest candidate is
+cached in a JSON file keyed by the GPU architecture and a workload signature.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+CANDIDATES = [(0, 1024), (0, 2048), (0, 4096), (1, 1024), (1, 2048), (1, 4096)]
+
+
+def cache_path():
+    return os.environ.get("MAPCORE_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "mapcore", "batch_tune.json"))
+
+
+def _arch():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name)
+
+
+def tune(signature, build, run_step, n_steps=3, candidates=CANDIDATES, use_cache=True):
+    """build() -> Batch on fresh maps; run_step(batch, k) runs step k (synchronous).
+    Returns (schedule, grid, timings {cand: median seconds})."""
+    import torch
+    key = f"{_arch()}|{signature}"
+    path = cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            c = cache[key]
+            return c["schedule"], c["grid"], {tuple(map(int, k.split(","))): v for k, v in c["timings"].items()}
+    timings = {}
+    for sched, grid in candidates:
+        batch = build()
+        batch.configure(sched, grid, True)
+        run_step(batch, 0)
+        ts = []
+        for k in range(1, n_steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run_step(batch, k)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        timings[(sched, grid)] = ts[len(ts) // 2]
+        for m in batch.maps:
+            m.close()
+        batch.close()
+    best = min(timings, key=timings.get)
+    cache[key] = {"schedule": best[0], "grid": best[1],
+                  "timings": {f"{k[0]},{k[1]}": v for k, v in timings.items()}}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    except OSError:
+        pass
+    return best[0], best[1], timings

@@ -1,0 +1,505 @@
+// Device bodies shared by the per-map kernels and the batched (many maps per launch)
+// kernels, so both run the same arithmetic for a map.
+//
+// Every value that is stored or decides which block, pixel or voxel is touched is
+// computed in fp32 with a fixed evaluation order (the library is built with
+// -ffp-contract=off); point-vs-pixel-boundary decisions are exact signs of fp64
+// products of fp32 operands; the segment walk is exact integer arithmetic.
+#pragma once
+#include "internal.h"
+
+namespace mc {
+
+constexpr int kThreads = 256;
+constexpr int kLdsKeys = 2048;                    // per-workgroup de-duplication table (16 KiB)
+constexpr int kKeysPerThread = kLdsKeys / kThreads;
+constexpr int kHalo = 9;
+constexpr int kHaloVoxels = kHalo * kHalo * kHalo;
+
+// ---------------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Workgroup exclusive prefix sum of one int per thread; returns the exclusive prefix and
+// writes the total to *total (all threads).  `tmp` holds kThreads / 64 ints.
+__device__ __forceinline__ int wg_scan(int v, int *tmp, int *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) tmp[wave] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const int t = tmp[w];
+        before += w < wave ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+// ---------------------------------------------------------------------------------
+// exact predicates and the nearest pixel
+// ---------------------------------------------------------------------------------
+
+// sign of ax*qy - ay*qx: the fp64 products of fp32 operands are exact, so the sign of the
+// correctly rounded difference is exact
+__device__ __forceinline__ double cross64(float ax, float ay, float qx, float qy)
+{
+    return (double)ax * (double)qy - (double)ay * (double)qx;
+}
+
+// Column c holds points strictly counter-clockwise of boundary c+1 and clockwise of, or
+// on, boundary c (boundary c lies between columns c-1 and c; ties go to the higher index).
+__device__ __forceinline__ bool col_holds(const LidarLUT &L, int c, float px, float py)
+{
+    int c1 = (c + 1 == L.cols) ? 0 : c + 1;
+    return cross64(L.bcx[c1], L.bcy[c1], px, py) > 0.0 && cross64(L.bcx[c], L.bcy[c], px, py) <= 0.0;
+}
+
+// nearest pixel of a sensor-frame point, or false
+__device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float py, float pz, int &row,
+                                              int &col)
+{
+    if (px == 0.0f && py == 0.0f) return false;
+    const float kPi = 3.14159265358979f;
+    float a = (kPi - atan2f(py, px)) * L.cols_over_2pi;
+    int g = (int)floorf(a + 0.5f);
+    g %= L.cols;
+    if (g < 0) g += L.cols;
+    int c = -1;
+    if (col_holds(L, g, px, py)) c = g;
+    else {
+        int gm = g == 0 ? L.cols - 1 : g - 1, gp = g + 1 == L.cols ? 0 : g + 1;
+        if (col_holds(L, gm, px, py)) c = gm;
+        else if (col_holds(L, gp, px, py)) c = gp;
+        else {
+            for (int k = 0; k < L.cols; ++k)
+                if (col_holds(L, k, px, py)) { c = k; break; }
+            if (c < 0) return false;
+        }
+    }
+    float rho = sqrtf(px * px + py * py);
+    // inside the vertical field of view: on or below boundary 0, strictly above boundary R
+    if (cross64(L.brc[0], L.brs[0], rho, pz) > 0.0) return false;
+    if (cross64(L.brc[L.rows], L.brs[L.rows], rho, pz) <= 0.0) return false;
+    // largest k in [0, rows-1] with the point on or below boundary k
+    int lo = 0, hi = L.rows - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cross64(L.brc[mid], L.brs[mid], rho, pz) <= 0.0) lo = mid;
+        else hi = mid - 1;
+    }
+    row = lo;
+    col = c;
+    return true;
+}
+
+__device__ __forceinline__ bool valid_return(float r, float r_max)
+{
+    return isfinite(r) && r > 0.0f && r <= r_max;
+}
+
+// ---------------------------------------------------------------------------------
+// allocation: band segment -> blocks, frame set, touched list
+// ---------------------------------------------------------------------------------
+
+// Claim a key in the frame set: 1 if this call inserted it (first in the frame), 0 if it
+// was there, -1 if the set is full.  Writes the set slot to *slot.
+__device__ __forceinline__ int frame_claim(const FrameView &f, unsigned long long key, uint32_t *slot)
+{
+    uint32_t i = hash_slot(key, f.fmask);
+    for (uint32_t n = 0; n <= f.fmask; ++n) {
+        unsigned long long cur = __atomic_load_n(&f.fkeys[i], __ATOMIC_RELAXED);
+        if (cur == key) return 0;
+        if (cur == kEmpty) {
+            unsigned long long prev = atomicCAS(&f.fkeys[i], kEmpty, key);
+            if (prev == kEmpty) {
+                *slot = i;
+                return 1;
+            }
+            if (prev == key) return 0;
+        }
+        i = (i + 1) & f.fmask;
+    }
+    return -1;
+}
+
+// Direct insert used only when a workgroup's LDS table overflows: one atomic per block.
+__device__ __forceinline__ void frame_insert_direct(const MapView &m, const FrameView &f, unsigned long long key)
+{
+    uint32_t fs;
+    const int c = frame_claim(f, key, &fs);
+    if (c < 0) atomicExch(&m.ctr->overflow, 1);
+    if (c <= 0) return;
+    const int s = hash_find(m, key);
+    const unsigned long long add = 1ull | (s < 0 ? (1ull << 32) : 0ull);
+    const unsigned long long old = atomicAdd(&m.ctr->touched_new, add);
+    const int idx = (int)(old & 0xFFFFFFFFull);
+    if (idx >= f.tk_cap) {
+        atomicExch(&m.ctr->overflow, 1);
+        return;
+    }
+    f.tk_key[idx] = key;
+    f.tk_fslot[idx] = (int)fs;
+    f.tk_slot[idx] = s;
+    f.tk_rank[idx] = s < 0 ? (int)(old >> 32) : -1;
+}
+
+__device__ __forceinline__ void lds_insert(unsigned long long *lk, const MapView &m, const FrameView &f,
+                                           unsigned long long key)
+{
+    uint32_t i = hash_slot(key, kLdsKeys - 1);
+    for (int n = 0; n < kLdsKeys; ++n) {
+        unsigned long long cur = lk[i];
+        if (cur == key) return;
+        if (cur == kEmpty) {
+            unsigned long long prev = atomicCAS(&lk[i], kEmpty, key);
+            if (prev == kEmpty || prev == key) return;
+        }
+        i = (i + 1) & (kLdsKeys - 1);
+    }
+    frame_insert_direct(m, f, key);  // table full: straight to the frame set
+}
+
+// The band segment of one pixel's valid return, in 2^-16-voxel fixed point (voxel v
+// spans [v, v+1) after the half-voxel shift), walked block by block: at each step the
+// axis whose next block boundary comes first advances.  Moves in the positive direction
+// happen at the crossing parameter (the boundary plane belongs to the next block); moves
+// in the negative direction happen just after it.  Axes with equal parameter and
+// direction class move together, so a segment through an edge or corner skips the side
+// blocks exactly as the half-open cells require.
+__device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapView &m, const FrameView &f,
+                                            const LidarLUT &L, const Pose &T, const float *__restrict__ range,
+                                            int pix)
+{
+    float r = range[pix];
+    if (!valid_return(r, L.r_max)) return;
+    const int k = pix / L.cols, c = pix - k * L.cols;
+    const float dx = L.ce[k] * L.cp[c], dy = L.ce[k] * L.sp[c], dz = L.se[k];
+    float s0 = r - m.tau;
+    if (!(s0 > 0.0f)) s0 = 0.0f;
+    const float s1 = r + m.tau;
+    long long Q0[3], Q1[3], b[3], be[3], d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float w = (T.m[4 * a] * dx + T.m[4 * a + 1] * dy) + T.m[4 * a + 2] * dz;
+        const float o = T.m[4 * a + 3];
+        const float p0 = o + s0 * w, p1 = o + s1 * w;
+        const float q0 = p0 / m.nu + 0.5f, q1 = p1 / m.nu + 0.5f;
+        Q0[a] = (long long)rintf(q0 * 65536.0f);
+        Q1[a] = (long long)rintf(q1 * 65536.0f);
+        b[a] = Q0[a] >> 19;   // arithmetic shift: floor division by one block
+        be[a] = Q1[a] >> 19;
+        d[a] = Q1[a] - Q0[a];
+    }
+    lds_insert(lk, m, f, pack_key((int)b[0], (int)b[1], (int)b[2]));
+    for (int step = 0; step < 64; ++step) {
+        if (b[0] == be[0] && b[1] == be[1] && b[2] == be[2]) break;
+        long long bn = 0, bm = 1;
+        int bcls = 2;
+        long long n[3], mm[3];
+        int cls[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cls[a] = 2;  // no event
+            if (b[a] == be[a]) continue;
+            if (d[a] > 0) {
+                n[a] = ((b[a] + 1) << 19) - Q0[a];
+                mm[a] = d[a];
+                cls[a] = 0;
+            } else {
+                n[a] = Q0[a] - (b[a] << 19);
+                mm[a] = -d[a];
+                cls[a] = 1;
+            }
+            bool earlier;
+            if (bcls == 2) earlier = true;
+            else {
+                long long lhs = n[a] * bm, rhs = bn * mm[a];
+                earlier = lhs < rhs || (lhs == rhs && cls[a] < bcls);
+            }
+            if (earlier) { bn = n[a]; bm = mm[a]; bcls = cls[a]; }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (cls[a] == bcls && n[a] * bm == bn * mm[a]) b[a] += d[a] > 0 ? 1 : -1;
+        lds_insert(lk, m, f, pack_key((int)b[0], (int)b[1], (int)b[2]));
+    }
+}
+
+// Claim the workgroup's de-duplicated blocks in the frame set; the first claimant of
+// each block in the frame appends it to the touched list (with its map slot, or its rank
+// among the frame's new blocks), with one list reservation per workgroup.
+__device__ __forceinline__ void alloc_flush(unsigned long long *lk, int *s_tmp, unsigned long long *s_base,
+                                            const MapView &m, const FrameView &f)
+{
+    unsigned long long key[kKeysPerThread];
+    uint32_t fslot[kKeysPerThread];
+    int mslot[kKeysPerThread];
+    int n_win = 0, n_new = 0;
+#pragma unroll
+    for (int j = 0; j < kKeysPerThread; ++j) {
+        key[j] = lk[threadIdx.x + j * kThreads];
+        mslot[j] = -2;  // not a winner
+        if (key[j] == kEmpty) continue;
+        const int c = frame_claim(f, key[j], &fslot[j]);
+        if (c < 0) atomicExch(&m.ctr->overflow, 1);
+        if (c <= 0) continue;
+        mslot[j] = hash_find(m, key[j]);
+        n_win++;
+        n_new += mslot[j] < 0;
+    }
+    int tot_win, tot_new;
+    const int off_win = wg_scan(n_win, s_tmp, &tot_win);
+    const int off_new = wg_scan(n_new, s_tmp, &tot_new);
+    if (threadIdx.x == 0)
+        *s_base = tot_win ? atomicAdd(&m.ctr->touched_new, ((unsigned long long)tot_new << 32) | (unsigned)tot_win)
+                          : 0ull;
+    __syncthreads();
+    int idx = (int)(*s_base & 0xFFFFFFFFull) + off_win;
+    int rank = (int)(*s_base >> 32) + off_new;
+#pragma unroll
+    for (int j = 0; j < kKeysPerThread; ++j) {
+        if (mslot[j] == -2) continue;
+        if (idx < f.tk_cap) {
+            f.tk_key[idx] = key[j];
+            f.tk_fslot[idx] = (int)fslot[j];
+            f.tk_slot[idx] = mslot[j];
+            f.tk_rank[idx] = mslot[j] < 0 ? rank : -1;
+        } else {
+            atomicExch(&m.ctr->overflow, 1);
+        }
+        idx++;
+        rank += mslot[j] < 0;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// TSDF integration (Eq. 5) with block commit and dirty marking
+// ---------------------------------------------------------------------------------
+
+// Frame state read once by every worker of the TSDF phase.
+struct FrameState {
+    int n_list, n_new, used;
+    uint32_t epoch;
+    bool ok;
+};
+
+__device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameView &f)
+{
+    const Counters *c = m.ctr;
+    const unsigned long long tn = c->touched_new;
+    FrameState s;
+    const int n_touched = (int)(tn & 0xFFFFFFFFull);
+    s.n_new = (int)(tn >> 32);
+    s.used = c->pool_used;
+    s.epoch = c->dirty_epoch;
+    s.ok = c->overflow == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
+    s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
+    return s;
+}
+
+// Publish a new block: reserve the slot with the busy bit, write the pool slot, then
+// release the key, so a concurrent lookup never reads a slot before it is written.
+__device__ __forceinline__ void hash_publish(const MapView &m, unsigned long long key, int slot)
+{
+    uint32_t i = hash_slot(key, m.hmask);
+    for (uint32_t n = 0; n <= m.hmask; ++n) {
+        unsigned long long prev = atomicCAS(&m.hkeys[i], kEmpty, key | kBusy);
+        if (prev == kEmpty) {
+            __hip_atomic_store(&m.hvals[i], slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&m.hkeys[i], key, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        i = (i + 1) & m.hmask;
+    }
+}
+
+// Lookup while blocks are being published: a published key returns its slot; a key still
+// being published (a block new in this frame) or an absent key returns -1.
+__device__ __forceinline__ int hash_find_published(const MapView &m, unsigned long long key)
+{
+    uint32_t i = hash_slot(key, m.hmask);
+    for (uint32_t n = 0; n <= m.hmask; ++n) {
+        unsigned long long k = __hip_atomic_load(&m.hkeys[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == key) return __hip_atomic_load(&m.hvals[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == kEmpty || k == (key | kBusy)) return -1;
+        i = (i + 1) & m.hmask;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void mark_dirty(const MapView &m, int slot, uint32_t epoch)
+{
+    uint32_t old = atomicExch(&m.dirty_flag[slot], epoch);
+    if (old != epoch) {
+        int i = atomicAdd(&m.ctr->n_dirty, 1);
+        m.dirty_list[i] = slot;
+    }
+}
+
+// Commit of touched entry e by one thread: clear its frame-set slot, and give a new block
+// its pool slot (after the used ones, in rank order) and publish it.  Returns the slot.
+__device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f, const FrameState &fs, int e,
+                                            unsigned long long key)
+{
+    f.fkeys[f.tk_fslot[e]] = kEmpty;  // the frame set is empty again at frame end
+    int slot = f.tk_slot[e];
+    if (fs.ok && slot < 0) {
+        slot = fs.used + f.tk_rank[e];
+        const int3 bc = unpack_key(key);
+        m.coords[slot] = make_int4(bc.x, bc.y, bc.z, 0);
+        hash_publish(m, key, slot);
+        f.tk_slot[e] = slot;
+    }
+    return slot;
+}
+
+// Dirty set: the block and its allocated lower neighbours b - e, e in {0,1}^3 (a
+// neighbour that is new in this frame is itself in the touched list and marks itself).
+__device__ __forceinline__ void mark_neighbours(const MapView &m, int j, int3 bc, int slot, uint32_t epoch)
+{
+    const int s = j == 0 ? slot
+                         : hash_find_published(m, pack_key(bc.x - (j & 1), bc.y - ((j >> 1) & 1), bc.z - ((j >> 2) & 1)));
+    if (s >= 0) mark_dirty(m, s, epoch);
+}
+
+// Projective TSDF update of voxel li of a block; returns true if it updated, and sets band.
+__device__ __forceinline__ bool tsdf_voxel(const MapView &m, const LidarLUT &L, const Pose &T,
+                                           const float *__restrict__ range, float2 *dwb, int3 bc, int li, bool &band)
+{
+    const float nu = m.nu, tau = m.tau, two_tau = m.tau + m.tau;
+    band = false;
+    const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
+    const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
+    const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
+    const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
+    const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
+    const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
+    int row, col;
+    if (px == 0.0f && py == 0.0f && pz == 0.0f) return false;
+    if (!nearest_pixel(L, px, py, pz, row, col)) return false;
+    const float r = range[row * L.cols + col];
+    if (!valid_return(r, L.r_max)) return false;
+    const float dist = sqrtf((px * px + py * py) + pz * pz);
+    const float psi = r - dist;
+    if (psi < -tau) return false;
+    float w = (psi + tau) / two_tau;
+    if (w > 1.0f) w = 1.0f;
+    if (w == 0.0f) return false;
+    const float gam = psi < tau ? psi : tau;
+    float2 v = dwb[li];
+    const float num = v.y * v.x + w * gam;
+    const float den = v.y + w;
+    v.x = num / den;
+    v.y = den;
+    dwb[li] = v;
+    band = fabsf(psi) <= tau;
+    return true;
+}
+
+// Close the frame (one thread, after every worker of the TSDF phase has finished):
+// commit the pool size, record the frame's counts, reset the per-frame counters.
+__device__ __forceinline__ void close_frame(const MapView &m, const FrameState &fs)
+{
+    Counters *c = m.ctr;
+    const unsigned long long upd = atomicAdd(&c->updates, 0ull);
+    if (fs.ok) {
+        c->pool_used = fs.used + fs.n_new;
+        c->frames += 1;
+        c->frame_ok = 1;
+        c->last_touched = fs.n_list;
+        c->last_new = fs.n_new;
+        c->last_updates = upd;
+    } else {
+        c->frame_ok = 0;
+        c->status = -2;  // MAP_ERR_CAPACITY, reported by the next synchronising call
+        c->last_touched = 0;  // a rejected frame leaves nothing to label
+        c->last_new = 0;
+        c->last_updates = 0;
+    }
+    c->touched_new = 0;
+    c->updates = 0;
+    c->votes = 0;
+    c->overflow = 0;
+}
+
+// ---------------------------------------------------------------------------------
+// label fusion (Eq. 6 as vote counts): one band voxel, every camera of the set in order
+// ---------------------------------------------------------------------------------
+
+__device__ __forceinline__ int label_voxel(const MapView &m, const CameraSet &cs, int slot, int3 bc, int li)
+{
+    const size_t vi = (size_t)slot * kBlockVoxels + li;
+    if (!(m.dw[vi].y > 0.0f)) return 0;
+    const float nu = m.nu;
+    const int L = m.n_classes;
+    const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
+    const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
+    uint16_t *cnt = m.counts + (size_t)slot * L * kBlockVoxels + li;
+    int fl = m.fused[vi];
+    const int fl0 = fl;
+    int votes = 0;
+    for (int ci = 0; ci < cs.n; ++ci) {
+        const Pose &T = cs.T[ci];
+        const Camera &cam = cs.cam[ci];
+        const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
+        const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
+        const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
+        const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
+        if (!(pz > 0.0f)) continue;
+        const float u = cam.fx * (px / pz) + cam.cx;
+        const float v = cam.fy * (py / pz) + cam.cy;
+        if (!(u >= 0.0f && u < (float)cam.width && v >= 0.0f && v < (float)cam.height)) continue;
+        const int iu = (int)u, iv = (int)v;
+        const int l = cs.img[ci][(size_t)iv * cam.width + iu];
+        if (l >= L) continue;
+        unsigned cl = cnt[(size_t)l * kBlockVoxels];
+        if (cl < 65535u) cl++;
+        cnt[(size_t)l * kBlockVoxels] = (uint16_t)cl;
+        const unsigned cf = fl == 255 ? 0u : cnt[(size_t)fl * kBlockVoxels];
+        if (l != fl && (cl > cf || (cl == cf && l < fl))) fl = l;
+        votes++;
+    }
+    if (fl != fl0) m.fused[vi] = (uint8_t)fl;
+    return votes;
+}
+
+// ---------------------------------------------------------------------------------
+// marching cubes of one block by one workgroup (see k_mesh.hip)
+// ---------------------------------------------------------------------------------
+
+__device__ __forceinline__ int halo_index(int x, int y, int z) { return x + kHalo * (y + kHalo * z); }
+
+// local base corner of cube edge e (axis e / 4, the other two offsets from e % 4)
+__device__ __forceinline__ int3 edge_base(int e)
+{
+    const int ax = e >> 2, j = e & 3;
+    if (ax == 0) return make_int3(0, j & 1, j >> 1);
+    if (ax == 1) return make_int3(j & 1, 0, j >> 1);
+    return make_int3(j & 1, j >> 1, 0);
+}
+
+struct MeshLds {
+    float2 dw[kHaloVoxels];
+    uint8_t fused[kHaloVoxels];
+    int nb[8];
+    int wsum[kThreads / 64];
+    unsigned long long base;
+};
+
+}  // namespace mc

@@ -11,25 +11,30 @@ constexpr int kFxShift = 16;                  // 2^-16 voxel fixed point
 constexpr long long kBlockFx = 8LL << kFxShift;  // one block edge in fixed point
 constexpr int kDomainVoxels = (1 << 19) - 64;    // |voxel index| bound of the map domain
 
-// Device-side counters of one map.
+// Device-side counters of one map.  Per-frame counters are reset on the device by the
+// last workgroup of the TSDF kernel, so a frame needs no bookkeeping launches.
 struct Counters {
-    int32_t n_touched;   // entries appended to the touched list this frame
-    int32_t n_new;       // of which absent from the map
+    unsigned long long touched_new; // this frame: low 32 bits |T_k| entries, high 32 bits new ones
     int32_t pool_used;   // allocated blocks
-    int32_t frame_ok;    // 1 if the current frame was accepted
+    int32_t frame_ok;    // 1 if the last frame was accepted
     int32_t n_dirty;     // entries of the dirty list
     uint32_t dirty_epoch;
     int32_t status;      // deferred error (MAP_ERR_CAPACITY) until read by the host
     int32_t frames;      // accepted frames
-    unsigned long long updates;     // U_k
+    unsigned long long updates;     // U_k being accumulated
     unsigned long long votes;       // label votes since the last LiDAR frame
-    unsigned long long tris;        // triangles of the current extraction
-    unsigned long long mesh_blocks; // blocks of the current extraction
+    unsigned long long tris[2];     // triangles of an extraction (parity-buffered)
+    unsigned long long mesh_blocks; // blocks of the last extraction
+    unsigned long long last_updates;
     int32_t last_touched;  // |T_k| of the last accepted frame (labels read it)
     int32_t last_new;
     int32_t overflow;      // touched list overflow (cannot happen with the sizing rule)
+    uint32_t tsdf_done;    // workgroup tickets
+    uint32_t mesh_done;
     int32_t pad;
 };
+
+constexpr unsigned long long kBusy = 1ull << 63;  // key being published (slot not yet written)
 
 // Block pool, hash and dirty set.
 struct MapView {
@@ -78,6 +83,14 @@ struct Pose {  // rows 0..2 of a row-major 4x4
 struct Camera {
     int32_t width, height;
     float fx, fy, cx, cy;
+};
+
+constexpr int kMaxCams = 8;
+struct CameraSet {  // cameras fused by one launch, in call order
+    int32_t n;
+    Camera cam[kMaxCams];
+    Pose T[kMaxCams];
+    const uint8_t *img[kMaxCams];
 };
 
 struct MeshOut {
@@ -129,19 +142,44 @@ __device__ inline int hash_find(const MapView &m, unsigned long long key)
 // ---------------------------------------------------------------------------------
 // launch wrappers (defined in the kernel sources)
 // ---------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------
+// batched steps: one launch per phase covers every map of the step
+// ---------------------------------------------------------------------------------
+constexpr int kMaxBatchMaps = 64;
+
+struct BatchMap {  // one map's frame in a batched step (device array, refreshed per step)
+    MapView v;
+    FrameView f;
+    LidarLUT lut;
+    Pose T;
+    const float *range;
+    CameraSet cams;
+    MeshOut out;
+    int32_t tile0, tiles;  // this map's allocation tiles in the step's tile space
+    int32_t parity;        // this map's extraction parity
+    int32_t pad;
+};
+
+struct BatchCtl {  // device
+    uint32_t queue[3];  // work queues: TSDF, labels, meshing
+    uint32_t done[4];   // workgroup tickets per phase
+    int32_t pre_t[kMaxBatchMaps + 1];  // prefix sums over maps: touched entries
+    int32_t pre_l[kMaxBatchMaps + 1];  // label entries
+    int32_t pre_d[kMaxBatchMaps + 1];  // dirty blocks
+    unsigned long long tris[kMaxBatchMaps];  // triangle count per map (read back)
+};
+
+hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, int n_maps, int total_tiles, int schedule, int grid,
+                        hipStream_t s);
+
 hipError_t launch_init_pool(const MapView &m, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_frame_begin(const MapView &m, hipStream_t s);
 hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
                         const float *range, hipStream_t s);
 hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
                        const float *range, int grid, hipStream_t s);
-hipError_t launch_finish(const MapView &m, const FrameView &f, int grid, hipStream_t s);
-hipError_t launch_labels(const MapView &m, const FrameView &f, const Camera &cam, const Pose &T,
-                         const uint8_t *labels, int grid, hipStream_t s);
-hipError_t launch_mesh_begin(const MapView &m, hipStream_t s);
-hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, int grid, hipStream_t s);
-hipError_t launch_mesh_end(const MapView &m, hipStream_t s);
+hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int grid, hipStream_t s);
+hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int grid, hipStream_t s);
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
                         uint8_t *valid, hipStream_t s);
 hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,

@@ -7,11 +7,9 @@
 //   g_j = 2 D grad D,  dL/dt = sum g_j,  dL/dw = J_l(w)^T sum (R p_j) x g_j,
 //   dL/dp_j = R^T g_j,
 // with J_l the left Jacobian of SO(3).  Per-pose sums are reduced in a fixed order.
-#include "internal.h"
+#include "device.h"
 
 namespace mc {
-
-constexpr int kThreads = 256;
 
 // trilinear sample at voxel-space point q; grad is dD/dx (already divided by nu)
 __device__ __forceinline__ bool sample(const MapView &m, float qx, float qy, float qz, float &D, float g[3])

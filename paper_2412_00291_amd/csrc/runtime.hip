@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -24,6 +26,8 @@ struct map_s {
     Counters *h_ctr = nullptr;  // pinned mirror for read-back
     hipStream_t last_stream = nullptr;
     bool has_scan = false;
+    int mesh_parity = 0;
+    int64_t last_tris = 0;
     std::string err;
     // LiDAR look-up tables (device) and the model they were built for
     float *lut_buf = nullptr;
@@ -383,14 +387,46 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     rc = ensure_frame_scratch(m, L, s);
     if (rc) return rc;
     const Pose T = to_pose(T_wl);
-    HIP_TRY(m, timed(m, MAP_K_SMALL, s, [&] { return launch_frame_begin(m->v, s); }));
     HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] { return launch_alloc(m->v, m->f, m->lut, T, range_dev, s); }));
     HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
         return launch_tsdf(m->v, m->f, m->lut, T, range_dev, grid_for(m->f.tk_cap, 1, 2048), s);
     }));
-    HIP_TRY(m, timed(m, MAP_K_FINISH, s, [&] { return launch_finish(m->v, m->f, grid_for(m->f.tk_cap, 256, 1024), s); }));
     m->last_stream = s;
     m->has_scan = true;
+    return MAP_OK;
+}
+
+static bool camera_ok(const camera_model *cam)
+{
+    return cam->width >= 1 && cam->height >= 1 && std::isfinite(cam->fx) && std::isfinite(cam->fy) &&
+           std::isfinite(cam->cx) && std::isfinite(cam->cy) && cam->fx != 0.0f && cam->fy != 0.0f;
+}
+
+extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_model *cams,
+                                          const uint8_t *const *labels_dev, const float *T_wc, void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (n < 1 || !cams || !labels_dev || !T_wc) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: bad arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!labels_dev[i]) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: NULL label image %d", i);
+        if (!camera_ok(&cams[i])) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: bad camera model %d", i);
+        if (!pose_ok(T_wc + 16 * i)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: pose %d is not rigid", i);
+    }
+    if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels: no LiDAR frame integrated yet");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    for (int i0 = 0; i0 < n; i0 += kMaxCams) {
+        CameraSet cs{};
+        cs.n = std::min(kMaxCams, n - i0);
+        for (int j = 0; j < cs.n; ++j) {
+            const camera_model &c = cams[i0 + j];
+            cs.cam[j] = Camera{c.width, c.height, c.fx, c.fy, c.cx, c.cy};
+            cs.T[j] = to_pose(T_wc + 16 * (i0 + j));
+            cs.img[j] = labels_dev[i0 + j];
+        }
+        HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] { return launch_labels(m->v, m->f, cs, grid_for(m->f.tk_cap, 1, 2048), s); }));
+    }
+    m->last_stream = s;
     return MAP_OK;
 }
 
@@ -399,20 +435,7 @@ extern "C" int map_integrate_labels(map_t *m, const camera_model *cam, const uin
 {
     if (!m) return MAP_ERR_INVALID_ARG;
     if (!cam || !labels_dev || !T_wc) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: NULL argument");
-    if (cam->width < 1 || cam->height < 1 || !std::isfinite(cam->fx) || !std::isfinite(cam->fy) ||
-        !std::isfinite(cam->cx) || !std::isfinite(cam->cy) || cam->fx == 0.0f || cam->fy == 0.0f)
-        return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: bad camera model");
-    if (!pose_ok(T_wc)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: pose is not a rigid transform");
-    if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels: no LiDAR frame integrated yet");
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(m, hipSetDevice(m->p.device));
-    Camera c{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
-    const Pose T = to_pose(T_wc);
-    HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
-        return launch_labels(m->v, m->f, c, T, labels_dev, grid_for(m->f.tk_cap, 1, 2048), s);
-    }));
-    m->last_stream = s;
-    return MAP_OK;
+    return map_integrate_labels_multi(m, 1, cam, &labels_dev, T_wc, stream);
 }
 
 extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab_dev, int64_t *edge_keys_dev,
@@ -425,17 +448,20 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
-    HIP_TRY(m, timed(m, MAP_K_SMALL, s, [&] { return launch_mesh_begin(m->v, s); }));
-    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] { return launch_mesh(m->v, mode, out, grid_for(m->p.max_blocks, 1, 2048), s); }));
+    const int parity = m->mesh_parity;
+    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
+        return launch_mesh(m->v, mode, parity, out, grid_for(m->p.max_blocks, 1, 2048), s);
+    }));
     HIP_TRY(m, hipMemcpyAsync(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(m, hipStreamSynchronize(s));
     m->last_stream = s;
-    const int64_t n = (int64_t)m->h_ctr->tris;
+    m->mesh_parity = 1 - parity;
+    const int64_t n = (int64_t)m->h_ctr->tris[parity];
     *n_tris = n;
+    m->last_tris = n;
     if (n > cap_tris)
         return fail(m, MAP_ERR_BUFFER_TOO_SMALL, "extract_mesh: %lld triangles, capacity %lld", (long long)n,
                     (long long)cap_tris);
-    if (mode == MAP_MESH_DIRTY) HIP_TRY(m, timed(m, MAP_K_SMALL, s, [&] { return launch_mesh_end(m->v, s); }));
     return MAP_OK;
 }
 
@@ -512,12 +538,12 @@ extern "C" int map_stats(map_t *m, map_frame_stats *out)
     int rc = read_counters(m);
     if (rc) return rc;
     const Counters &c = *m->h_ctr;
-    out->touched = c.frame_ok ? c.last_touched : c.n_touched;
-    out->new_blocks = c.frame_ok ? c.last_new : 0;
-    out->updates = (int64_t)c.updates;
+    out->touched = c.last_touched;
+    out->new_blocks = c.last_new;
+    out->updates = (int64_t)c.last_updates;
     out->votes = (int64_t)c.votes;
     out->mesh_blocks = (int64_t)c.mesh_blocks;
-    out->triangles = (int64_t)c.tris;
+    out->triangles = m->last_tris;
     out->allocated = c.pool_used;
     out->frames = c.frames;
     return take_status(m);
@@ -609,4 +635,191 @@ extern "C" int map_read_block(map_t *m, int32_t bx, int32_t by, int32_t bz, floa
         return 1;
     }
     return 0;
+}
+
+// ---------------------------------------------------------------------------------
+// batched steps
+// ---------------------------------------------------------------------------------
+
+struct map_batch_s {
+    std::vector<map_t *> maps;
+    int device = 0;
+    BatchMap *d_desc = nullptr, *h_desc = nullptr;
+    BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
+    int schedule = 0, grid = 2048;
+    bool use_graph = true;
+    // one executable graph per step shape (map count, tile count, schedule, grid, stream)
+    std::map<std::tuple<int, int, int, int, hipStream_t>, hipGraphExec_t> graphs;
+    std::string err;
+};
+
+static void batch_free(map_batch_t *b)
+{
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+    b->graphs.clear();
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_ctl) (void)hipFree(b->d_ctl);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+}
+
+extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out)
+{
+    if (!maps || !out || n < 1 || n > kMaxBatchMaps)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "map_batch_create: need 1..%d maps", kMaxBatchMaps);
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!maps[i]) return fail(nullptr, MAP_ERR_INVALID_ARG, "map_batch_create: NULL map %d", i);
+        if (maps[i]->p.device != maps[0]->p.device)
+            return fail(nullptr, MAP_ERR_INVALID_ARG, "map_batch_create: maps on different devices");
+        for (int j = 0; j < i; ++j)
+            if (maps[j] == maps[i]) return fail(nullptr, MAP_ERR_INVALID_ARG, "map_batch_create: map %d repeated", i);
+    }
+    map_batch_t *b = new map_batch_s();
+    b->maps.assign(maps, maps + n);
+    b->device = maps[0]->p.device;
+    bool ok = hipSetDevice(b->device) == hipSuccess &&
+              hipMalloc(&b->d_desc, kMaxBatchMaps * sizeof(BatchMap)) == hipSuccess &&
+              hipMalloc(&b->d_ctl, sizeof(BatchCtl)) == hipSuccess &&
+              hipHostMalloc((void **)&b->h_desc, kMaxBatchMaps * sizeof(BatchMap), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+        std::memset(b->h_ctl, 0, sizeof(BatchCtl));
+        ok = hipMemcpy(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+        batch_free(b);
+        delete b;
+        return fail(nullptr, MAP_ERR_DEVICE, "map_batch_create: device allocation failed");
+    }
+    *out = b;
+    return MAP_OK;
+}
+
+extern "C" int map_batch_configure(map_batch_t *b, int32_t schedule, int32_t grid, int32_t use_graph)
+{
+    if (!b || (schedule != 0 && schedule != 1) || grid < 64 || grid > 65536) return MAP_ERR_INVALID_ARG;
+    b->schedule = schedule;
+    b->grid = grid;
+    b->use_graph = use_graph != 0;
+    return MAP_OK;
+}
+
+extern "C" void map_batch_destroy(map_batch_t *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+    delete b;
+}
+
+extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32_t n, int64_t *n_tris, void *stream)
+{
+    if (!b || !items || !n_tris || n < 1 || n > (int)b->maps.size()) return MAP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(b->device) != hipSuccess) return MAP_ERR_DEVICE;
+    std::vector<char> seen(b->maps.size(), 0);
+    // validate every item before touching any map (same checks as the plain calls)
+    for (int i = 0; i < n; ++i) {
+        const map_batch_item &it = items[i];
+        if (it.map_index < 0 || it.map_index >= (int)b->maps.size() || seen[it.map_index]) {
+            b->err = "map_batch_step: bad or repeated map index";
+            return MAP_ERR_INVALID_ARG;
+        }
+        seen[it.map_index] = 1;
+        map_t *m = b->maps[it.map_index];
+        const lidar_model *L = it.lidar;
+        if (!L || !L->elev_rad || !it.range_dev || !it.T_wl || L->rows < 2 || L->cols < 8 || !(L->r_max > 0.0f) ||
+            !std::isfinite(L->r_max) || !pose_ok(it.T_wl) || it.n_cams < 0 || it.n_cams > kMaxCams ||
+            (it.n_cams > 0 && (!it.cams || !it.labels_dev || !it.T_wc)) || it.cap_tris < 0 ||
+            (it.cap_tris > 0 && (!it.pos_dev || !it.lab_dev))) {
+            b->err = "map_batch_step: bad item";
+            return fail(m, MAP_ERR_INVALID_ARG, "map_batch_step: bad item %d", i);
+        }
+        const double lim = (double)m->p.voxel_size * kDomainVoxels;
+        for (int a = 0; a < 3; ++a)
+            if (std::fabs((double)it.T_wl[4 * a + 3]) + (double)L->r_max + (double)m->p.truncation >= lim)
+                return fail(m, MAP_ERR_INVALID_ARG, "map_batch_step: scan reaches outside the map domain");
+        for (int c = 0; c < it.n_cams; ++c)
+            if (!it.labels_dev[c] || !camera_ok(&it.cams[c]) || !pose_ok(it.T_wc + 16 * c))
+                return fail(m, MAP_ERR_INVALID_ARG, "map_batch_step: bad camera %d of item %d", c, i);
+    }
+    int tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        const map_batch_item &it = items[i];
+        map_t *m = b->maps[it.map_index];
+        int rc = ensure_lut(m, it.lidar, s);
+        if (rc) return rc;
+        rc = ensure_frame_scratch(m, it.lidar, s);
+        if (rc) return rc;
+        BatchMap &d = b->h_desc[i];
+        d.v = m->v;
+        d.f = m->f;
+        d.lut = m->lut;
+        d.T = to_pose(it.T_wl);
+        d.range = it.range_dev;
+        d.cams = CameraSet{};
+        d.cams.n = it.n_cams;
+        for (int c = 0; c < it.n_cams; ++c) {
+            const camera_model &cm = it.cams[c];
+            d.cams.cam[c] = Camera{cm.width, cm.height, cm.fx, cm.fy, cm.cx, cm.cy};
+            d.cams.T[c] = to_pose(it.T_wc + 16 * c);
+            d.cams.img[c] = it.labels_dev[c];
+        }
+        d.out = MeshOut{it.pos_dev, it.lab_dev, (long long *)it.edge_keys_dev, (long long)it.cap_tris};
+        d.tile0 = tiles;
+        d.tiles = (it.lidar->rows * it.lidar->cols + 255) / 256;
+        d.parity = m->mesh_parity;
+        tiles += d.tiles;
+    }
+    auto fail_b = [&](hipError_t e, const char *what) {
+        b->err = std::string(what) + ": " + hipGetErrorString(e);
+        return MAP_ERR_DEVICE;
+    };
+    hipError_t e = hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(BatchMap), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_b(e, "descriptor upload");
+    if (b->use_graph && s != nullptr) {  // the legacy default stream cannot be captured
+        const auto key = std::make_tuple(n, tiles, b->schedule, b->grid, s);
+        auto itg = b->graphs.find(key);
+        if (itg == b->graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return fail_b(e, "graph capture");
+            hipError_t le = launch_batch(b->d_desc, b->d_ctl, n, tiles, b->schedule, b->grid, s);
+            e = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess) return fail_b(le, "batched launch");
+            if (e != hipSuccess) return fail_b(e, "graph capture end");
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail_b(e, "graph instantiate");
+            itg = b->graphs.emplace(key, ge).first;
+        }
+        e = hipGraphLaunch(itg->second, s);
+        if (e != hipSuccess) return fail_b(e, "graph launch");
+    } else {
+        e = launch_batch(b->d_desc, b->d_ctl, n, tiles, b->schedule, b->grid, s);
+        if (e != hipSuccess) return fail_b(e, "batched launch");
+    }
+    e = hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_b(e, "result read-back");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_b(e, "step");
+    int rc = MAP_OK;
+    for (int i = 0; i < n; ++i) {
+        map_t *m = b->maps[items[i].map_index];
+        const int64_t t = (int64_t)b->h_ctl->tris[i];
+        n_tris[i] = t;
+        m->last_tris = t;
+        m->mesh_parity = 1 - m->mesh_parity;
+        m->has_scan = true;
+        m->last_stream = s;
+        if (t > items[i].cap_tris) {
+            fail(m, MAP_ERR_BUFFER_TOO_SMALL, "map_batch_step: %lld triangles, capacity %lld", (long long)t,
+                 (long long)items[i].cap_tris);
+            rc = MAP_ERR_BUFFER_TOO_SMALL;
+        }
+    }
+    return rc;
 }

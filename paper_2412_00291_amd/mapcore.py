@@ -46,6 +46,13 @@ class _Camera(ctypes.Structure):
                 ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("map_index", ctypes.c_int32), ("lidar", ctypes.c_void_p), ("range_dev", ctypes.c_void_p),
+                ("T_wl", ctypes.c_void_p), ("n_cams", ctypes.c_int32), ("cams", ctypes.c_void_p),
+                ("labels_dev", ctypes.c_void_p), ("T_wc", ctypes.c_void_p), ("pos_dev", ctypes.c_void_p),
+                ("lab_dev", ctypes.c_void_p), ("edge_keys_dev", ctypes.c_void_p), ("cap_tris", ctypes.c_int64)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("touched", "new_blocks", "updates", "votes", "mesh_blocks",
                                               "triangles", "allocated", "frames")]
@@ -57,6 +64,7 @@ _sig = {
     "map_destroy": (None, [_P]),
     "map_integrate_lidar": (ctypes.c_int, [_P, ctypes.POINTER(_Lidar), _P, _P, _P]),
     "map_integrate_labels": (ctypes.c_int, [_P, ctypes.POINTER(_Camera), _P, _P, _P]),
+    "map_integrate_labels_multi": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P]),
     "map_extract_mesh": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
     "map_query_sdf": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "map_sdf_pose_adjoint": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
@@ -68,10 +76,14 @@ _sig = {
     "map_download": (_I64, [_P, _I64, _P, _P, _P, _P, _P]),
     "map_read_block": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
     "map_profile": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "map_batch_create": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_P)]),
+    "map_batch_configure": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "map_batch_step": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "map_batch_destroy": (None, [_P]),
     "map_profile_read": (ctypes.c_int, [_P, _P, _P]),
 }
 
-KERNEL_NAMES = ["alloc", "tsdf", "finish", "labels", "mesh", "query", "adjoint", "small"]
+KERNEL_NAMES = ["alloc", "tsdf", "labels", "mesh", "query", "adjoint", "batch"]
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -172,6 +184,24 @@ def map_integrate_labels(handle, cam: CameraModel, labels_dev, T_wc, stream=None
     keep, T = _pose(T_wc)
     return _lib.map_integrate_labels(handle, ctypes.byref(cam._c()), _dev(labels_dev, torch.uint8, "labels"), T,
                                      _stream(stream))
+
+
+def map_integrate_labels_multi(handle, cams, labels_dev, T_wc, stream=None):
+    """n cameras in one call: cams [n] CameraModel, labels_dev [n] uint8 device tensors,
+    T_wc [n] 4x4 poses; equal to n single-camera calls in order."""
+    import torch
+    n = len(cams)
+    if len(labels_dev) != n or len(T_wc) != n:
+        raise ValueError("cams, labels and poses differ in length")
+    carr = (_Camera * n)(*[c._c() for c in cams])
+    ptrs = (ctypes.c_void_p * n)()
+    for i, (c, l) in enumerate(zip(cams, labels_dev)):
+        if l.numel() != c.width * c.height:
+            raise ValueError("label image size does not match the camera model")
+        ptrs[i] = _dev(l, torch.uint8, "labels").value
+    T = np.ascontiguousarray(np.stack([np.asarray(t, np.float32).reshape(16) for t in T_wc]))
+    return _lib.map_integrate_labels_multi(handle, n, ctypes.cast(carr, _P), ctypes.cast(ptrs, _P),
+                                           T.ctypes.data, _stream(stream))
 
 
 def map_extract_mesh(handle, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=None):
@@ -316,6 +346,9 @@ class Map:
     def integrate_labels(self, cam, labels_dev, T_wc, stream=None):
         return self._check(map_integrate_labels(self.h, cam, labels_dev, T_wc, stream))
 
+    def integrate_labels_multi(self, cams, labels_dev, T_wc, stream=None):
+        return self._check(map_integrate_labels_multi(self.h, cams, labels_dev, T_wc, stream))
+
     def extract_mesh(self, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=None, allow_small=False):
         st, n = map_extract_mesh(self.h, mode, pos_dev, lab_dev, edge_keys_dev, stream)
         self._check(st, (MAP_OK, MAP_ERR_BUFFER_TOO_SMALL) if allow_small else (MAP_OK,))
@@ -351,3 +384,90 @@ class Map:
 
     def read_block(self, b):
         return map_read_block(self.h, b, self.n_classes)
+
+
+# ----------------------------------------------------------------------------------------
+# batched steps
+# ----------------------------------------------------------------------------------------
+
+def map_batch_create(handles):
+    """Returns (status, batch handle)."""
+    n = len(handles)
+    arr = (_P * n)(*[h.value if isinstance(h, _P) else h for h in handles])
+    b = _P()
+    st = _lib.map_batch_create(ctypes.cast(arr, _P), n, ctypes.byref(b))
+    return st, b
+
+
+def map_batch_configure(batch, schedule, grid, use_graph=True):
+    return _lib.map_batch_configure(batch, int(schedule), int(grid), int(bool(use_graph)))
+
+
+def map_batch_destroy(batch):
+    _lib.map_batch_destroy(batch)
+
+
+def map_batch_step(batch, items, stream=None):
+    """items: list of dicts with map_index, lidar (LidarModel), range (device tensor), T_wl,
+    and optionally cams (CameraModel list), labels (device tensors), T_wc (poses), pos, lab,
+    keys (mesh outputs).  Returns (status, [triangles per item])."""
+    import torch
+    n = len(items)
+    arr = (_BatchItem * n)()
+    keep = []
+    for i, it in enumerate(items):
+        L = it["lidar"]._c()
+        T = np.ascontiguousarray(np.asarray(it["T_wl"], np.float32).reshape(16))
+        cams = it.get("cams") or []
+        nc = len(cams)
+        carr = (_Camera * max(nc, 1))(*[c._c() for c in cams])
+        ptrs = (ctypes.c_void_p * max(nc, 1))()
+        for c, l in enumerate(it.get("labels") or []):
+            ptrs[c] = _dev(l, torch.uint8, "labels").value
+        Tc = (np.ascontiguousarray(np.stack([np.asarray(t, np.float32).reshape(16) for t in it["T_wc"]]))
+              if nc else np.zeros(16, np.float32))
+        pos, lab, keys = it.get("pos"), it.get("lab"), it.get("keys")
+        cap = 0 if pos is None else pos.shape[0]
+        arr[i] = _BatchItem(int(it["map_index"]), ctypes.addressof(L), _dev(it["range"], torch.float32, "range").value,
+                            T.ctypes.data, nc, ctypes.addressof(carr), ctypes.addressof(ptrs), Tc.ctypes.data,
+                            _dev(pos, torch.float32, "pos").value if cap else None,
+                            _dev(lab, torch.uint8, "lab").value if cap else None,
+                            _dev(keys, torch.int64, "keys").value if (cap and keys is not None) else None, cap)
+        keep += [L, T, carr, ptrs, Tc]
+    out = np.zeros(n, np.int64)
+    st = _lib.map_batch_step(batch, ctypes.cast(arr, _P), n, out.ctypes.data, _stream(stream))
+    return st, out.tolist()
+
+
+class Batch:
+    """Maps stepped together; each keeps the state its own plain calls would give."""
+
+    def __init__(self, maps, schedule=0, grid=2048, use_graph=True):
+        self.maps = list(maps)
+        st, self.h = map_batch_create([m.h for m in self.maps])
+        if st != MAP_OK:
+            raise MapError(st, map_last_error(None))
+        self.configure(schedule, grid, use_graph)
+
+    def configure(self, schedule, grid, use_graph=True):
+        st = map_batch_configure(self.h, schedule, grid, use_graph)
+        if st != MAP_OK:
+            raise MapError(st, "bad batch configuration")
+        self.schedule, self.grid, self.use_graph = schedule, grid, use_graph
+
+    def step(self, items, stream=None, allow_small=False):
+        st, n = map_batch_step(self.h, items, stream)
+        if st not in ((MAP_OK, MAP_ERR_BUFFER_TOO_SMALL) if allow_small else (MAP_OK,)):
+            raise MapError(st, "batched step failed")
+        return st, n
+
+    def close(self):
+        if getattr(self, "h", None):
+            map_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

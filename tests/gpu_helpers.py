@@ -48,6 +48,25 @@ def compare_state(m, om, d_tol=1e-5, exact_labels=True):
     return {"blocks": len(gkeys), "voxels": n_obs, "non_identical": n_diff}
 
 
+def canonical_mesh(pos, lab, keys):
+    """Triangles as rows [3 edge keys, 3 labels, 9 position bit patterns], lexicographically
+    sorted: two meshes are equal as multisets iff these matrices are equal."""
+    n = len(keys)
+    rows = np.concatenate([np.asarray(keys, np.int64).reshape(n, 3),
+                           np.asarray(lab, np.int64).reshape(n, 3),
+                           np.ascontiguousarray(pos, np.float32).reshape(n, 9).view(np.int32).astype(np.int64)], axis=1)
+    if n == 0:
+        return rows
+    order = np.lexsort(rows.T[::-1])
+    return rows[order]
+
+
+def sorted_download(m):
+    d = m.download()
+    order = np.lexsort(d["coords"].T[::-1])
+    return {k: v[order] for k, v in d.items()}
+
+
 def gpu_mesh(m, mode, cap=None):
     import torch
     from paper_2412_00291_amd import MAP_OK, MAP_ERR_BUFFER_TOO_SMALL
@@ -70,18 +89,16 @@ def compare_mesh(gm, om_mesh, tol_vox=1e-4, voxel=None):
     same edge key within tol_vox voxel."""
     pos, lab, keys = om_mesh
     assert gm["n"] == len(keys), (gm["n"], len(keys))
-    from collections import Counter
-    g = Counter(zip(map(tuple, gm["keys"].tolist()), map(tuple, gm["lab"].tolist())))
-    o = Counter(zip(map(tuple, keys.tolist()), map(tuple, lab.tolist())))
-    assert g == o, (sum((g - o).values()), sum((o - g).values()))
-    gv = dict(zip(gm["keys"].reshape(-1).tolist(), gm["pos"].reshape(-1, 3)))
-    ov = dict(zip(keys.reshape(-1).tolist(), pos.reshape(-1, 3)))
+    a = canonical_mesh(np.zeros((gm["n"], 3, 3), np.float32), gm["lab"], gm["keys"])[:, :6]
+    b = canonical_mesh(np.zeros((len(keys), 3, 3), np.float32), lab, keys)[:, :6]
+    assert np.array_equal(a, b)
     err = 0.0
-    if len(ov):
-        ks = list(ov.keys())
-        a = np.array([gv[k] for k in ks], np.float64)
-        b = np.array([ov[k] for k in ks], np.float64)
-        err = float(np.abs(a - b).max())
+    if len(keys):
+        gk, gi = np.unique(gm["keys"].reshape(-1), return_index=True)
+        ok_, oi = np.unique(keys.reshape(-1), return_index=True)
+        assert np.array_equal(gk, ok_)
+        err = float(np.abs(gm["pos"].reshape(-1, 3)[gi].astype(np.float64) -
+                           pos.reshape(-1, 3)[oi].astype(np.float64)).max())
     if voxel is not None:
         assert err <= tol_vox * voxel, err
     return {"triangles": gm["n"], "max_err_vox": err / voxel if voxel else err}

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_helpers import camera_model, compare_mesh, compare_state, gpu_mesh, lidar_model
+from tests.gpu_helpers import camera_model, canonical_mesh, compare_mesh, compare_state, gpu_mesh, lidar_model, sorted_download
 
 pytestmark = pytest.mark.gpu
 
@@ -162,6 +162,32 @@ def test_buffer_too_small_keeps_dirty_set(torch_dev):
     compare_mesh(full, (pos, lab, keys), voxel=w.voxel)
 
 
+def test_multi_camera_call_equals_sequential_calls(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import Map
+    w = synth.street_workload(n_frames=2)
+    outs = []
+    for multi in (False, True):
+        m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+        for k in range(2):
+            f = w.frame(k)
+            m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
+            labs = [torch.from_numpy(np.ascontiguousarray(lab)).to(dev) for _, lab, _ in f.cams]
+            cams = [camera_model(c) for _, _, c in f.cams]
+            Ts = [T for T, _, _ in f.cams]
+            if multi:
+                m.integrate_labels_multi(cams, labs, Ts)
+            else:
+                for c, l, T in zip(cams, labs, Ts):
+                    m.integrate_labels(c, l, T)
+        st, s = m.stats()
+        outs.append((s["votes"], sorted_download(m)))
+        m.close()
+    assert outs[0][0] == outs[1][0] > 0
+    for k in ("coords", "D", "W", "fused", "counts"):
+        assert np.array_equal(outs[0][1][k], outs[1][1][k]), k
+
+
 def test_two_runs_bit_identical(torch_dev):
     torch, dev = torch_dev
     from paper_2412_00291_amd import Map
@@ -174,15 +200,13 @@ def test_two_runs_bit_identical(torch_dev):
             m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
             for T, lab, cam in f.cams:
                 m.integrate_labels(camera_model(cam), torch.from_numpy(np.ascontiguousarray(lab)).to(dev), T)
-        d = m.download()
-        order = np.lexsort(d["coords"].T[::-1])
+        d = sorted_download(m)
         mesh = gpu_mesh(m, 1)
-        tri = sorted(zip(map(tuple, mesh["keys"].tolist()), mesh["pos"].reshape(len(mesh["keys"]), 9).tolist()))
-        outs.append(({k: v[order] for k, v in d.items()}, tri))
+        outs.append((d, canonical_mesh(mesh["pos"], mesh["lab"], mesh["keys"])))
         m.close()
     for k in ("coords", "D", "W", "fused", "counts"):
         assert np.array_equal(outs[0][0][k].view(np.uint8), outs[1][0][k].view(np.uint8)), k
-    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][1], outs[1][1])
 
 
 def _tri_blocks(keys):
@@ -197,7 +221,6 @@ def test_incremental_union_equals_full_remesh(torch_dev):
     """Meshing the dirty blocks after frames 0, 2 and 3 (frame 1's blocks wait for the
     next extraction) and keeping each block's latest mesh equals meshing everything."""
     torch, dev = torch_dev
-    from collections import Counter
     from tests.gpu_helpers import step_log
     w = synth.street_workload(n_frames=4)
     m, _ = _pair(w)
@@ -206,7 +229,6 @@ def test_incremental_union_equals_full_remesh(torch_dev):
     for k in range(4):
         f = w.frame(k, with_labels=False)
         m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
-        step_log(f"incremental: frame {k} enqueued")
         allocated = {tuple(b) for b in m.block_coords()}
         for b in m.touched_coords():
             for e in range(8):
@@ -217,21 +239,25 @@ def test_incremental_union_equals_full_remesh(torch_dev):
         if k == 1:
             continue
         gm = gpu_mesh(m, 0)
-        step_log(f"incremental: frame {k} meshed {gm['n']} triangles")
         st, s = m.stats()
         assert s["mesh_blocks"] == len(pending)
-        blk = _tri_blocks(gm["keys"])
+        rows = canonical_mesh(gm["pos"], gm["lab"], gm["keys"])
+        rb = _tri_blocks(rows[:, :3]).astype(np.int64)
+        bkey = ((rb[:, 0] + (1 << 20)) << 42) | ((rb[:, 1] + (1 << 20)) << 21) | (rb[:, 2] + (1 << 20))
+        order = np.argsort(bkey, kind="stable")
+        uniq, starts = np.unique(bkey[order], return_index=True)
         for b in pending:
-            acc[b] = []
-        for t, b in enumerate(map(tuple, blk.tolist())):
+            acc[b] = rows[:0]  # re-meshed: the block's previous triangles are replaced
+        for u, g in zip(uniq.tolist(), np.split(rows[order], starts[1:])):
+            b = ((u >> 42) - (1 << 20), ((u >> 21) & 0x1FFFFF) - (1 << 20), (u & 0x1FFFFF) - (1 << 20))
             assert b in pending
-            acc[b].append((tuple(gm["keys"][t].tolist()), tuple(gm["lab"][t].tolist()), gm["pos"][t].tobytes()))
+            acc[b] = g
         pending = set()
     full = gpu_mesh(m, 1)
-    want = Counter(zip(map(tuple, full["keys"].tolist()), map(tuple, full["lab"].tolist()),
-                       [p.tobytes() for p in full["pos"]]))
-    got = Counter(x for v in acc.values() for x in v)
-    assert got == want and full["n"] > 100000
+    want = canonical_mesh(full["pos"], full["lab"], full["keys"])
+    got = np.concatenate([v for v in acc.values() if len(v)])
+    got = got[np.lexsort(got.T[::-1])]
+    assert np.array_equal(got, want) and full["n"] > 100000
     m.close()
 
 
