@@ -130,6 +130,11 @@ int map_integrate_labels_multi(map_t *map, int32_t n, const camera_model *cams,
 int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
                      int64_t *edge_keys_dev, int64_t cap_tris, int64_t *n_tris, void *stream);
 
+/* Work split of the per-map TSDF, label and meshing kernels (each 0 or 1): 0 = one
+ * workgroup per block, 1 = one wavefront per block.  Results are identical either way;
+ * only the speed differs.  Default 0, 0, 0. */
+int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
+
 /* Trilinear query of the distance field at n world points (device float [n][3]):
  * sdf [n] float, grad [n][3] float (nullable), valid [n] uint8.  A point is valid when
  * all eight voxels around it are observed; invalid points get 0.  Asynchronous. */

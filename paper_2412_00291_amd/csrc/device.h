@@ -292,52 +292,67 @@ __device__ __forceinline__ void alloc_flush(unsigned long long *lk, int *s_tmp, 
 // TSDF integration (Eq. 5) with block commit and dirty marking
 // ---------------------------------------------------------------------------------
 
-// Frame state read once by every worker of the TSDF phase.
+// Frame state read once by every worker of the TSDF phase (device-coherent loads: the
+// counters were last written by atomics).
 struct FrameState {
     int n_list, n_new, used;
     uint32_t epoch;
     bool ok;
 };
 
+template <class T>
+__device__ __forceinline__ T coherent_load(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this thread's earlier memory operations (including atomics whose result is
+// unused) have completed, so a following ticket atomic is performed after them.
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 __device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameView &f)
 {
-    const Counters *c = m.ctr;
-    const unsigned long long tn = c->touched_new;
+    Counters *c = m.ctr;
+    const unsigned long long tn = coherent_load(&c->touched_new);
     FrameState s;
     const int n_touched = (int)(tn & 0xFFFFFFFFull);
     s.n_new = (int)(tn >> 32);
-    s.used = c->pool_used;
-    s.epoch = c->dirty_epoch;
-    s.ok = c->overflow == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
+    s.used = coherent_load(&c->pool_used);
+    s.epoch = coherent_load(&c->dirty_epoch);
+    s.ok = coherent_load(&c->overflow) == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
     s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
     return s;
 }
 
-// Publish a new block: reserve the slot with the busy bit, write the pool slot, then
-// release the key, so a concurrent lookup never reads a slot before it is written.
-__device__ __forceinline__ void hash_publish(const MapView &m, unsigned long long key, int slot)
+// Insert a new block: claim the slot with a CAS on the key, then write the pool slot and
+// the inserting call's number.  No other launch reads these before this one ends.
+__device__ __forceinline__ void hash_insert_new(const MapView &m, unsigned long long key, int slot, uint32_t frame_id)
 {
     uint32_t i = hash_slot(key, m.hmask);
     for (uint32_t n = 0; n <= m.hmask; ++n) {
-        unsigned long long prev = atomicCAS(&m.hkeys[i], kEmpty, key | kBusy);
+        unsigned long long prev = atomicCAS(&m.hkeys[i], kEmpty, key);
         if (prev == kEmpty) {
-            __hip_atomic_store(&m.hvals[i], slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&m.hkeys[i], key, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            m.hvals[i] = slot;
+            m.hframe[i] = frame_id;
             return;
         }
         i = (i + 1) & m.hmask;
     }
 }
 
-// Lookup while blocks are being published: a published key returns its slot; a key still
-// being published (a block new in this frame) or an absent key returns -1.
-__device__ __forceinline__ int hash_find_published(const MapView &m, unsigned long long key)
+// Slot of a block that existed before this call, or -1 (absent, or inserted by this call:
+// its slot may not be written yet, and it is in the touched list anyway).  A key seen
+// before its tag is written reads the initial tag ~0 and is also taken as new.
+__device__ __forceinline__ int hash_find_old(const MapView &m, unsigned long long key, uint32_t frame_id)
 {
     uint32_t i = hash_slot(key, m.hmask);
     for (uint32_t n = 0; n <= m.hmask; ++n) {
-        unsigned long long k = __hip_atomic_load(&m.hkeys[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == key) return __hip_atomic_load(&m.hvals[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == kEmpty || k == (key | kBusy)) return -1;
+        const unsigned long long k = m.hkeys[i];
+        if (k == key) {
+            const uint32_t fr = m.hframe[i];
+            return (fr == ~0u || fr == frame_id) ? -1 : m.hvals[i];
+        }
+        if (k == kEmpty) return -1;
         i = (i + 1) & m.hmask;
     }
     return -1;
@@ -353,9 +368,9 @@ __device__ __forceinline__ void mark_dirty(const MapView &m, int slot, uint32_t 
 }
 
 // Commit of touched entry e by one thread: clear its frame-set slot, and give a new block
-// its pool slot (after the used ones, in rank order) and publish it.  Returns the slot.
+// its pool slot (after the used ones, in rank order) and insert it.  Returns the slot.
 __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f, const FrameState &fs, int e,
-                                            unsigned long long key)
+                                            unsigned long long key, uint32_t frame_id)
 {
     f.fkeys[f.tk_fslot[e]] = kEmpty;  // the frame set is empty again at frame end
     int slot = f.tk_slot[e];
@@ -363,7 +378,7 @@ __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f
         slot = fs.used + f.tk_rank[e];
         const int3 bc = unpack_key(key);
         m.coords[slot] = make_int4(bc.x, bc.y, bc.z, 0);
-        hash_publish(m, key, slot);
+        hash_insert_new(m, key, slot, frame_id);
         f.tk_slot[e] = slot;
     }
     return slot;
@@ -371,10 +386,12 @@ __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f
 
 // Dirty set: the block and its allocated lower neighbours b - e, e in {0,1}^3 (a
 // neighbour that is new in this frame is itself in the touched list and marks itself).
-__device__ __forceinline__ void mark_neighbours(const MapView &m, int j, int3 bc, int slot, uint32_t epoch)
+__device__ __forceinline__ void mark_neighbours(const MapView &m, int j, int3 bc, int slot, uint32_t epoch,
+                                                uint32_t frame_id)
 {
     const int s = j == 0 ? slot
-                         : hash_find_published(m, pack_key(bc.x - (j & 1), bc.y - ((j >> 1) & 1), bc.z - ((j >> 2) & 1)));
+                         : hash_find_old(m, pack_key(bc.x - (j & 1), bc.y - ((j >> 1) & 1), bc.z - ((j >> 2) & 1)),
+                                         frame_id);
     if (s >= 0) mark_dirty(m, s, epoch);
 }
 

@@ -34,8 +34,6 @@ struct Counters {
     int32_t pad;
 };
 
-constexpr unsigned long long kBusy = 1ull << 63;  // key being published (slot not yet written)
-
 // Block pool, hash and dirty set.
 struct MapView {
     float2 *dw;               // [max_blocks][512] (D, W)
@@ -44,6 +42,7 @@ struct MapView {
     int4 *coords;             // [max_blocks] block coordinates per slot
     unsigned long long *hkeys;  // [hmask + 1]
     int32_t *hvals;           // [hmask + 1]
+    uint32_t *hframe;         // [hmask + 1] integration call that inserted the key (~0: none)
     uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
     int32_t *dirty_list;      // [max_blocks]
     Counters *ctr;
@@ -157,7 +156,7 @@ struct BatchMap {  // one map's frame in a batched step (device array, refreshed
     MeshOut out;
     int32_t tile0, tiles;  // this map's allocation tiles in the step's tile space
     int32_t parity;        // this map's extraction parity
-    int32_t pad;
+    uint32_t frame_id;     // this map's integration call number
 };
 
 struct BatchCtl {  // device
@@ -177,9 +176,11 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v
 hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
                         const float *range, hipStream_t s);
 hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                       const float *range, int grid, hipStream_t s);
-hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int grid, hipStream_t s);
-hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int grid, hipStream_t s);
+                       const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s);
+hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int schedule, int grid,
+                         hipStream_t s);
+hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int schedule, int grid,
+                       hipStream_t s);
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
                         uint8_t *valid, hipStream_t s);
 hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,

@@ -27,7 +27,7 @@ __device__ __forceinline__ int find_map(const int32_t *pre, int n, int i)
 __device__ __forceinline__ bool last_of_grid(uint32_t *ticket, int *s_last)
 {
     if (threadIdx.x == 0) {
-        __threadfence();
+        wait_memory();  // this workgroup's atomics land before its ticket
         *s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
     }
     __syncthreads();
@@ -54,7 +54,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_alloc(BatchMap *maps, BatchC
     __syncthreads();
     alloc_flush(lk, s_tmp, &s_base, B.v, B.f);
     if (last_of_grid(&ctl->done[0], &s_last) && threadIdx.x == 0) {
-        __threadfence();
         int acc = 0;
         for (int m = 0; m < n; ++m) {
             ctl->pre_t[m] = acc;
@@ -100,17 +99,17 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
         const unsigned long long key = B.f.tk_key[e];
         int slot = 0;
         if (kSched == 0) {
-            if (threadIdx.x == 0) s_slot[0] = commit_entry(B.v, B.f, fs, e, key);
+            if (threadIdx.x == 0) s_slot[0] = commit_entry(B.v, B.f, fs, e, key, B.frame_id);
             __syncthreads();
             slot = s_slot[0];
         } else {
-            if (lane == 0) slot = commit_entry(B.v, B.f, fs, e, key);
+            if (lane == 0) slot = commit_entry(B.v, B.f, fs, e, key, B.frame_id);
             slot = __shfl(slot, 0, 64);
         }
         if (fs.ok) {
             const int3 bc = unpack_key(key);
             const int rank = kSched == 0 ? (int)threadIdx.x : lane;
-            if (rank < 8) mark_neighbours(B.v, rank, bc, slot, fs.epoch);
+            if (rank < 8) mark_neighbours(B.v, rank, bc, slot, fs.epoch, B.frame_id);
             float2 *dwb = B.v.dw + (size_t)slot * kBlockVoxels;
             unsigned long long upd = 0;
             constexpr int kWidth = kSched == 0 ? kThreads : 64;
@@ -131,7 +130,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
     for (int m = threadIdx.x; m < n; m += kThreads)
         if (s_upd[m]) atomicAdd(&maps[m].v.ctr->updates, s_upd[m]);
     if (last_of_grid(&ctl->done[1], &s_last) && threadIdx.x == 0) {
-        __threadfence();
         int acc_l = 0, acc_d = 0;
         for (int m = 0; m < n; ++m) {
             const BatchMap &B = maps[m];
@@ -139,8 +137,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
             ctl->pre_l[m] = acc_l;
             acc_l += B.v.ctr->last_touched;
             ctl->pre_d[m] = acc_d;
-            acc_d += B.v.ctr->n_dirty;
-            B.v.ctr->mesh_blocks = (unsigned long long)B.v.ctr->n_dirty;
+            const int nd = coherent_load(&B.v.ctr->n_dirty);
+            acc_d += nd;
+            B.v.ctr->mesh_blocks = (unsigned long long)nd;
             B.v.ctr->tris[B.parity] = 0;
             B.v.ctr->tris[1 - B.parity] = 0;
         }
@@ -222,7 +221,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh(BatchMap *maps, BatchCt
         mesh_block(B.v, B.v.dirty_list[item - ctl->pre_d[mi]], B.out, &B.v.ctr->tris[B.parity], S);
     }
     if (last_of_grid(&ctl->done[3], &s_last) && threadIdx.x == 0) {
-        __threadfence();
         for (int m = 0; m < n; ++m) {
             const BatchMap &B = maps[m];
             unsigned long long *tris = &B.v.ctr->tris[B.parity];

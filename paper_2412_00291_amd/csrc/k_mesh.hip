@@ -6,10 +6,15 @@
 
 namespace mc {
 
+template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_mesh(MapView m, int mode, int parity, MeshOut out)
 {
-    __shared__ MeshLds S;
+    // kSched 0: one workgroup per block; 1: one wavefront per block (own LDS region)
+    constexpr size_t kLds = kSched == 0 ? sizeof(MeshLds) : (kThreads / 64) * sizeof(MeshLdsWave);
+    __shared__ __align__(16) char smem[kLds];
     __shared__ int s_last;
+    MeshLds &S = *reinterpret_cast<MeshLds *>(smem);
+    MeshLdsWave *SW = reinterpret_cast<MeshLdsWave *>(smem);
     Counters *c = m.ctr;
     unsigned long long *tris = &c->tris[parity];
     const int nblk = mode == 0 ? c->n_dirty : c->pool_used;
@@ -17,23 +22,31 @@ __global__ __launch_bounds__(kThreads) void k_mesh(MapView m, int mode, int pari
         c->mesh_blocks = (unsigned long long)nblk;
         c->tris[1 - parity] = 0;
     }
-    for (int e = blockIdx.x; e < nblk; e += gridDim.x)
-        mesh_block(m, mode == 0 ? m.dirty_list[e] : e, out, tris, S);
+    if (kSched == 0) {
+        for (int e = blockIdx.x; e < nblk; e += gridDim.x)
+            mesh_block(m, mode == 0 ? m.dirty_list[e] : e, out, tris, S);
+    } else {
+        const int wave = threadIdx.x >> 6;
+        for (int e = blockIdx.x * (kThreads / 64) + wave; e < nblk; e += gridDim.x * (kThreads / 64))
+            mesh_block_wave(m, mode == 0 ? m.dirty_list[e] : e, out, tris, SW[wave]);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        __threadfence();
+        wait_memory();  // every triangle reservation lands before the ticket
         s_last = atomicAdd(&c->mesh_done, 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (s_last && threadIdx.x == 0) {
-        __threadfence();
         close_extraction(m, mode, tris, out.cap);
         c->mesh_done = 0;
     }
 }
 
-hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int grid, hipStream_t s)
+hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int schedule, int grid,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mesh, dim3(grid), dim3(kThreads), 0, s, m, mode, parity, out);
+    if (schedule == 0) hipLaunchKernelGGL(k_mesh<0>, dim3(grid), dim3(kThreads), 0, s, m, mode, parity, out);
+    else hipLaunchKernelGGL(k_mesh<1>, dim3(grid), dim3(kThreads), 0, s, m, mode, parity, out);
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ struct map_s {
     bool has_scan = false;
     int mesh_parity = 0;
     int64_t last_tris = 0;
+    uint32_t frame_id = 0;  // integration calls so far (tags hash insertions)
+    int sched[3] = {0, 0, 0};  // TSDF, labels, meshing: 0 workgroup / 1 wavefront per block
     std::string err;
     // LiDAR look-up tables (device) and the model they were built for
     float *lut_buf = nullptr;
@@ -85,7 +87,7 @@ static void free_all(map_t *m)
     for (hipEvent_t e : m->prof_free) (void)hipEventDestroy(e);
     m->prof_pending.clear();
     m->prof_free.clear();
-    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.dirty_flag,
+    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.hframe, m->v.dirty_flag,
                     m->v.dirty_list, m->v.ctr, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->lut_buf, m->partial};
     for (void *p : ptrs)
@@ -227,6 +229,7 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&v.coords, nb * sizeof(int4)));
     CREATE_TRY(hipMalloc(&v.hkeys, hcap * sizeof(unsigned long long)));
     CREATE_TRY(hipMalloc(&v.hvals, hcap * sizeof(int32_t)));
+    CREATE_TRY(hipMalloc(&v.hframe, hcap * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.dirty_flag, nb * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.dirty_list, nb * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&v.ctr, sizeof(Counters)));
@@ -235,6 +238,7 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMemsetAsync(v.counts, 0, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t), s));
     CREATE_TRY(hipMemsetAsync(v.coords, 0, nb * sizeof(int4), s));
     CREATE_TRY(hipMemsetAsync(v.dirty_flag, 0, nb * sizeof(uint32_t), s));
+    CREATE_TRY(hipMemsetAsync(v.hframe, 0xFF, hcap * sizeof(uint32_t), s));  // no insertion yet
     CREATE_TRY(launch_init_pool(v, s));
     CREATE_TRY(launch_fill_u64(v.hkeys, hcap, kEmpty, s));
     std::memset(m->h_ctr, 0, sizeof(Counters));
@@ -388,8 +392,9 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     if (rc) return rc;
     const Pose T = to_pose(T_wl);
     HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] { return launch_alloc(m->v, m->f, m->lut, T, range_dev, s); }));
+    const uint32_t fid = m->frame_id++;
     HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
-        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, grid_for(m->f.tk_cap, 1, 2048), s);
+        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, 2048), s);
     }));
     m->last_stream = s;
     m->has_scan = true;
@@ -424,7 +429,9 @@ extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_mode
             cs.T[j] = to_pose(T_wc + 16 * (i0 + j));
             cs.img[j] = labels_dev[i0 + j];
         }
-        HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] { return launch_labels(m->v, m->f, cs, grid_for(m->f.tk_cap, 1, 2048), s); }));
+        HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
+            return launch_labels(m->v, m->f, cs, m->sched[1], grid_for(m->f.tk_cap, 1, 2048), s);
+        }));
     }
     m->last_stream = s;
     return MAP_OK;
@@ -450,7 +457,7 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
     const int parity = m->mesh_parity;
     HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
-        return launch_mesh(m->v, mode, parity, out, grid_for(m->p.max_blocks, 1, 2048), s);
+        return launch_mesh(m->v, mode, parity, out, m->sched[2], grid_for(m->p.max_blocks, 1, 2048), s);
     }));
     HIP_TRY(m, hipMemcpyAsync(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(m, hipStreamSynchronize(s));
@@ -462,6 +469,16 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     if (n > cap_tris)
         return fail(m, MAP_ERR_BUFFER_TOO_SMALL, "extract_mesh: %lld triangles, capacity %lld", (long long)n,
                     (long long)cap_tris);
+    return MAP_OK;
+}
+
+extern "C" int map_set_schedule(map_t *m, int32_t tsdf, int32_t labels, int32_t mesh)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    const int v[3] = {tsdf, labels, mesh};
+    for (int i = 0; i < 3; ++i)
+        if (v[i] != 0 && v[i] != 1) return fail(m, MAP_ERR_INVALID_ARG, "set_schedule: schedules are 0 or 1");
+    for (int i = 0; i < 3; ++i) m->sched[i] = v[i];
     return MAP_OK;
 }
 
@@ -771,6 +788,7 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         d.tile0 = tiles;
         d.tiles = (it.lidar->rows * it.lidar->cols + 255) / 256;
         d.parity = m->mesh_parity;
+        d.frame_id = m->frame_id++;
         tiles += d.tiles;
     }
     auto fail_b = [&](hipError_t e, const char *what) {

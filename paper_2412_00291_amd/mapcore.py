@@ -76,6 +76,7 @@ _sig = {
     "map_download": (_I64, [_P, _I64, _P, _P, _P, _P, _P]),
     "map_read_block": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
     "map_profile": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "map_set_schedule": (ctypes.c_int, [_P, _I32, _I32, _I32]),
     "map_batch_create": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_P)]),
     "map_batch_configure": (ctypes.c_int, [_P, _I32, _I32, _I32]),
     "map_batch_step": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
@@ -375,6 +376,9 @@ class Map:
 
     def download(self, with_counts=True):
         return map_download(self.h, self.n_classes, with_counts)
+
+    def set_schedule(self, tsdf, labels, mesh):
+        return self._check(_lib.map_set_schedule(self.h, int(tsdf), int(labels), int(mesh)))
 
     def profile(self, mask):
         return self._check(map_profile(self.h, mask))

@@ -84,15 +84,16 @@ def test_sphere_closed_form_and_three_views(torch_dev):
 
 
 def test_street_window(torch_dev):
-    """Three consecutive 64x2048 frames with four 1280x720 label images each; state and
-    per-frame dirty meshes compared after every frame."""
+    """A 10-frame window of 64x2048 frames with four 1280x720 label images each; per-frame
+    dirty meshes and counters compared after every frame, full state after frames 0, 4, 9."""
     torch, dev = torch_dev
-    w = synth.street_workload(n_frames=3)
+    w = synth.street_workload(n_frames=10)
     m, om = _pair(w)
-    for k in range(3):
+    for k in range(10):
         f = w.frame(k)
         _step(torch, m, om, w, f)
-        rep = compare_state(m, om)
+        if k in (0, 4, 9):
+            rep = compare_state(m, om)
         gm = gpu_mesh(m, 0)
         st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
         compare_mesh(gm, (pos, lab, keys), voxel=w.voxel)
@@ -160,6 +161,23 @@ def test_buffer_too_small_keeps_dirty_set(torch_dev):
     assert full["status"] == 0 and full["n"] == small["n"]
     st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
     compare_mesh(full, (pos, lab, keys), voxel=w.voxel)
+
+
+def test_wavefront_schedules_match_oracle(torch_dev):
+    """The wavefront-per-block variants of the TSDF, label and meshing kernels give the
+    oracle's state and meshes (two street frames, four cameras)."""
+    torch, dev = torch_dev
+    w = synth.street_workload(n_frames=2)
+    m, om = _pair(w)
+    m.set_schedule(1, 1, 1)
+    for k in range(2):
+        f = w.frame(k)
+        _step(torch, m, om, w, f)
+        compare_state(m, om)
+        gm = gpu_mesh(m, 0)
+        st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
+        compare_mesh(gm, (pos, lab, keys), voxel=w.voxel)
+    m.close()
 
 
 def test_multi_camera_call_equals_sequential_calls(torch_dev):

@@ -1,0 +1,78 @@
+"""CPU tests of host-side logic: the batch autotuner's choice and cache, and argument
+validation of the C ABI entry points (no GPU work is launched)."""
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2412_00291_amd", "libmapcore.so")
+
+
+class _FakeBatch:
+    def __init__(self):
+        self.maps = []
+        self.cfg = None
+
+    def configure(self, sched, grid, use_graph):
+        self.cfg = (sched, grid)
+
+    def close(self):
+        pass
+
+
+def test_autotuner_picks_fastest_and_caches(tmp_path, monkeypatch):
+    import time
+    from paper_2412_00291_amd import autotune
+    monkeypatch.setenv("MAPCORE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "_arch", lambda: "gfx950")
+
+    class _T:  # stands in for torch.cuda.synchronize
+        class cuda:
+            @staticmethod
+            def synchronize():
+                pass
+    monkeypatch.setitem(__import__("sys").modules, "torch", _T)
+    cost = {(0, 1024): 0.004, (0, 2048): 0.002, (1, 1024): 0.003}
+    built = []
+
+    def build():
+        b = _FakeBatch()
+        built.append(b)
+        return b
+
+    def run_step(b, k):
+        time.sleep(cost[b.cfg])
+
+    sched, grid, timings = autotune.tune("sig-a", build, run_step, n_steps=2, candidates=list(cost))
+    assert (sched, grid) == (0, 2048) and len(built) == 3
+    data = json.load(open(tmp_path / "tune.json"))
+    assert data["gfx950|sig-a"]["grid"] == 2048
+    built.clear()
+    assert autotune.tune("sig-a", build, run_step, candidates=list(cost))[:2] == (0, 2048)
+    assert not built  # served from the cache
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_create_rejects_bad_parameters():
+    from paper_2412_00291_amd import MAP_ERR_INVALID_ARG, map_create, map_last_error
+    for args in ((0.0, 0.3, 1000, 19), (0.1, 0.0, 1000, 19), (0.1, 7.0, 1000, 19), (0.1, 0.3, 0, 19),
+                 (0.1, 0.3, 1000, 0), (0.1, 0.3, 1000, 255), (float("nan"), 0.3, 1000, 19)):
+        st, h = map_create(*args, device=0, stream=0)
+        assert st == MAP_ERR_INVALID_ARG and not h.value
+        assert "map_create" in map_last_error(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_null_handles_are_rejected():
+    import ctypes
+    from paper_2412_00291_amd import MAP_ERR_INVALID_ARG
+    from paper_2412_00291_amd.mapcore import _lib
+    assert _lib.map_sync(None) == MAP_ERR_INVALID_ARG
+    assert _lib.map_integrate_lidar(None, None, None, None, None) == MAP_ERR_INVALID_ARG
+    assert _lib.map_batch_step(None, None, 0, None, None) == MAP_ERR_INVALID_ARG
+    assert _lib.map_set_schedule(None, 0, 0, 0) == MAP_ERR_INVALID_ARG
+    _lib.map_destroy(None)
+    _lib.map_batch_destroy(None)
+    n = ctypes.c_int64(0)
+    assert _lib.map_extract_mesh(None, 0, None, None, None, 0, ctypes.byref(n), None) == MAP_ERR_INVALID_ARG
