@@ -66,8 +66,9 @@ __device__ __forceinline__ double cross64(float ax, float ay, float qx, float qy
 // on, boundary c (boundary c lies between columns c-1 and c; ties go to the higher index).
 __device__ __forceinline__ bool col_holds(const LidarLUT &L, int c, float px, float py)
 {
-    int c1 = (c + 1 == L.cols) ? 0 : c + 1;
-    return cross64(L.bcx[c1], L.bcy[c1], px, py) > 0.0 && cross64(L.bcx[c], L.bcy[c], px, py) <= 0.0;
+    const int c1 = (c + 1 == L.cols) ? 0 : c + 1;
+    const float2 b1 = L.bc[c1], b0 = L.bc[c];
+    return cross64(b1.x, b1.y, px, py) > 0.0 && cross64(b0.x, b0.y, px, py) <= 0.0;
 }
 
 // nearest pixel of a sensor-frame point, or false
@@ -92,18 +93,30 @@ __device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float
             if (c < 0) return false;
         }
     }
-    float rho = sqrtf(px * px + py * py);
+    const float rho = sqrtf(px * px + py * py);
     // inside the vertical field of view: on or below boundary 0, strictly above boundary R
-    if (cross64(L.brc[0], L.brs[0], rho, pz) > 0.0) return false;
-    if (cross64(L.brc[L.rows], L.brs[L.rows], rho, pz) <= 0.0) return false;
-    // largest k in [0, rows-1] with the point on or below boundary k
-    int lo = 0, hi = L.rows - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (cross64(L.brc[mid], L.brs[mid], rho, pz) <= 0.0) lo = mid;
-        else hi = mid - 1;
+    const float2 top = L.br[0], bot = L.br[L.rows];
+    if (cross64(top.x, top.y, rho, pz) > 0.0) return false;
+    if (cross64(bot.x, bot.y, rho, pz) <= 0.0) return false;
+    // The row is the largest k in [0, rows-1] with the point on or below boundary k (the
+    // boundaries descend with k).  Start from the elevation's guess and walk: up while the
+    // point is above boundary k (boundary 0 stops it), then down while it is on or below
+    // boundary k+1.  Only the exact predicates decide, so the guess affects speed only.
+    int k = (int)floorf((L.el_top - atan2f(pz, rho)) * L.rows_over_fov);
+    k = k < 0 ? 0 : (k > L.rows - 1 ? L.rows - 1 : k);
+    for (;;) {
+        if (k == 0) break;
+        const float2 b = L.br[k];
+        if (cross64(b.x, b.y, rho, pz) <= 0.0) break;
+        --k;
     }
-    row = lo;
+    for (;;) {
+        if (k + 1 >= L.rows) break;
+        const float2 b = L.br[k + 1];
+        if (cross64(b.x, b.y, rho, pz) > 0.0) break;
+        ++k;
+    }
+    row = k;
     col = c;
     return true;
 }
@@ -243,19 +256,34 @@ __device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapVie
 
 // Claim the workgroup's de-duplicated blocks in the frame set; the first claimant of
 // each block in the frame appends it to the touched list (with its map slot, or its rank
-// among the frame's new blocks), with one list reservation per workgroup.
+// among the frame's new blocks), with one list reservation per workgroup.  The LDS table
+// is compacted first so that the claims (a dependent chain of global operations each)
+// spread over all threads instead of one chain per table slot.
 __device__ __forceinline__ void alloc_flush(unsigned long long *lk, int *s_tmp, unsigned long long *s_base,
                                             const MapView &m, const FrameView &f)
 {
     unsigned long long key[kKeysPerThread];
+    int n_mine = 0;
+#pragma unroll
+    for (int j = 0; j < kKeysPerThread; ++j) {
+        key[j] = lk[threadIdx.x + j * kThreads];
+        n_mine += key[j] != kEmpty;
+    }
+    int n_keys;
+    int o = wg_scan(n_mine, s_tmp, &n_keys);  // its barriers also order the reads above
+#pragma unroll
+    for (int j = 0; j < kKeysPerThread; ++j)
+        if (key[j] != kEmpty) lk[o++] = key[j];
+    __syncthreads();
     uint32_t fslot[kKeysPerThread];
     int mslot[kKeysPerThread];
     int n_win = 0, n_new = 0;
 #pragma unroll
     for (int j = 0; j < kKeysPerThread; ++j) {
-        key[j] = lk[threadIdx.x + j * kThreads];
+        const int i = threadIdx.x + j * kThreads;
         mslot[j] = -2;  // not a winner
-        if (key[j] == kEmpty) continue;
+        if (i >= n_keys) continue;
+        key[j] = lk[i];
         const int c = frame_claim(f, key[j], &fslot[j]);
         if (c < 0) atomicExch(&m.ctr->overflow, 1);
         if (c <= 0) continue;
@@ -292,13 +320,6 @@ __device__ __forceinline__ void alloc_flush(unsigned long long *lk, int *s_tmp, 
 // TSDF integration (Eq. 5) with block commit and dirty marking
 // ---------------------------------------------------------------------------------
 
-// Frame state read once by every worker of the TSDF phase (device-coherent loads: the
-// counters were last written by atomics).
-struct FrameState {
-    int n_list, n_new, used;
-    uint32_t epoch;
-    bool ok;
-};
 
 template <class T>
 __device__ __forceinline__ T coherent_load(T *p)
@@ -310,6 +331,8 @@ __device__ __forceinline__ T coherent_load(T *p)
 // unused) have completed, so a following ticket atomic is performed after them.
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Frame state after allocation (device-coherent loads: the counters were last written by
+// atomics).
 __device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameView &f)
 {
     Counters *c = m.ctr;
@@ -358,13 +381,21 @@ __device__ __forceinline__ int hash_find_old(const MapView &m, unsigned long lon
     return -1;
 }
 
-__device__ __forceinline__ void mark_dirty(const MapView &m, int slot, uint32_t epoch)
+// Mark slot s dirty (s < 0: nothing) and append it to the dirty list if this frame had
+// not marked it yet, with one list reservation per wavefront.  Every lane of the wave
+// calls it, all with the same map.
+__device__ __forceinline__ void dirty_append_wave(const MapView &m, int s, uint32_t epoch)
 {
-    uint32_t old = atomicExch(&m.dirty_flag[slot], epoch);
-    if (old != epoch) {
-        int i = atomicAdd(&m.ctr->n_dirty, 1);
-        m.dirty_list[i] = slot;
-    }
+    bool app = false;
+    if (s >= 0) app = atomicExch(&m.dirty_flag[s], epoch) != epoch;
+    const unsigned long long mask = __ballot(app);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&m.ctr->n_dirty, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (app) m.dirty_list[base + __popcll(mask & ((1ull << lane) - 1ull))] = s;
 }
 
 // Commit of touched entry e by one thread: clear its frame-set slot, and give a new block
@@ -386,13 +417,11 @@ __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f
 
 // Dirty set: the block and its allocated lower neighbours b - e, e in {0,1}^3 (a
 // neighbour that is new in this frame is itself in the touched list and marks itself).
-__device__ __forceinline__ void mark_neighbours(const MapView &m, int j, int3 bc, int slot, uint32_t epoch,
-                                                uint32_t frame_id)
+// Returns the slot that neighbour j of the block at bc (slot `slot`) marks, or -1.
+__device__ __forceinline__ int neighbour_slot(const MapView &m, int j, int3 bc, int slot, uint32_t frame_id)
 {
-    const int s = j == 0 ? slot
-                         : hash_find_old(m, pack_key(bc.x - (j & 1), bc.y - ((j >> 1) & 1), bc.z - ((j >> 2) & 1)),
-                                         frame_id);
-    if (s >= 0) mark_dirty(m, s, epoch);
+    if (j == 0) return slot;
+    return hash_find_old(m, pack_key(bc.x - (j & 1), bc.y - ((j >> 1) & 1), bc.z - ((j >> 2) & 1)), frame_id);
 }
 
 // Projective TSDF update of voxel li of a block; returns true if it updated, and sets band.
@@ -427,6 +456,27 @@ __device__ __forceinline__ bool tsdf_voxel(const MapView &m, const LidarLUT &L, 
     dwb[li] = v;
     band = fabsf(psi) <= tau;
     return true;
+}
+
+// The TSDF update of one touched block's voxels by one worker of kWidth lanes (rank is
+// the lane's index in the worker); records the block's band bits.  Returns the updates.
+template <int kWidth>
+__device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const FrameView &f, const LidarLUT &L,
+                                                         const Pose &T, const float *__restrict__ range, int e,
+                                                         unsigned long long key, int slot, int rank)
+{
+    const int3 bc = unpack_key(key);
+    float2 *dwb = m.dw + (size_t)slot * kBlockVoxels;
+    unsigned long long upd = 0;
+#pragma unroll
+    for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
+        const int li = it * kWidth + rank;
+        bool band;
+        upd += tsdf_voxel(m, L, T, range, dwb, bc, li, band);
+        const unsigned long long bits = __ballot(band);
+        if ((threadIdx.x & 63) == 0) f.band[(size_t)e * 8 + (li >> 6)] = bits;
+    }
+    return upd;
 }
 
 // Close the frame (one thread, after every worker of the TSDF phase has finished):

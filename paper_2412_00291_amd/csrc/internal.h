@@ -68,11 +68,13 @@ struct FrameView {
 struct LidarLUT {
     const float *ce, *se;   // ray elevation cos / sin, [rows]
     const float *cp, *sp;   // ray azimuth cos / sin, [cols]
-    const float *bcx, *bcy; // azimuth boundary between columns j-1 and j, [cols]
-    const float *brc, *brs; // elevation boundary j (rows + 1 of them)
+    const float2 *bc;       // azimuth boundary between columns j-1 and j as (cos, sin), [cols]
+    const float2 *br;       // elevation boundary j as (cos, sin), [rows + 1]
     int32_t rows, cols;
     float r_max;
     float cols_over_2pi;    // initial column guess scale
+    float el_top;           // elevation of boundary 0 (initial row guess)
+    float rows_over_fov;    // rows / (elevation of boundary 0 - elevation of boundary rows)
 };
 
 struct Pose {  // rows 0..2 of a row-major 4x4
@@ -159,9 +161,16 @@ struct BatchMap {  // one map's frame in a batched step (device array, refreshed
     uint32_t frame_id;     // this map's integration call number
 };
 
+// A frame's allocation outcome, read by every worker of its TSDF phase.
+struct FrameState {
+    int32_t n_list, n_new, used;
+    uint32_t epoch;
+    int32_t ok;
+};
+
 struct BatchCtl {  // device
-    uint32_t queue[3];  // work queues: TSDF, labels, meshing
     uint32_t done[4];   // workgroup tickets per phase
+    FrameState fs[kMaxBatchMaps];      // per-map frame state after allocation
     int32_t pre_t[kMaxBatchMaps + 1];  // prefix sums over maps: touched entries
     int32_t pre_l[kMaxBatchMaps + 1];  // label entries
     int32_t pre_d[kMaxBatchMaps + 1];  // dirty blocks

@@ -1,10 +1,11 @@
 // Batched step over many maps of uneven size: one launch per phase (allocation, TSDF,
 // labels, meshing) covers every map of the step, so a step is four launches (one graph
-// launch when captured) instead of four per map.  Workgroups pull (map, item) pairs from
-// device queues laid out by prefix sums over the maps; each item runs the same device
-// body as the per-map kernels, so every map ends bit-identical to its own plain calls.
-// The last workgroup of each phase does the per-map bookkeeping and lays out the next
-// phase's queue.
+// launch when captured) instead of four per map.  Each phase's items (pixel tiles,
+// touched entries, dirty blocks) are numbered across the maps by prefix sums, and the
+// grid strides over them statically; each item runs the same device body as the
+// per-map kernels, so every map ends bit-identical to its own plain calls.  The last
+// workgroup of each phase does the per-map bookkeeping and lays out the next phase's
+// prefix sums.
 //
 // Schedules for the TSDF and label phases: 0 = one workgroup per touched block (two
 // voxels per thread), 1 = one wavefront per touched block (eight voxels per lane, four
@@ -56,11 +57,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_alloc(BatchMap *maps, BatchC
     if (last_of_grid(&ctl->done[0], &s_last) && threadIdx.x == 0) {
         int acc = 0;
         for (int m = 0; m < n; ++m) {
+            const FrameState fs = frame_state(maps[m].v, maps[m].f);
+            ctl->fs[m] = fs;
             ctl->pre_t[m] = acc;
-            acc += frame_state(maps[m].v, maps[m].f).n_list;
+            acc += fs.n_list;
         }
         ctl->pre_t[n] = acc;
-        ctl->queue[0] = 0;
         ctl->done[0] = 0;
     }
 }
@@ -69,58 +71,78 @@ __global__ __launch_bounds__(kThreads) void k_batch_alloc(BatchMap *maps, BatchC
 // TSDF phase
 // ---------------------------------------------------------------------------------
 
+// Copy the prefix sums over maps into LDS (n + 1 entries).
+__device__ __forceinline__ void load_prefix(int *dst, const int32_t *src, int n)
+{
+    for (int i = threadIdx.x; i <= n; i += kThreads) dst[i] = src[i];
+    __syncthreads();
+}
+
+// Append this lane's dirty slot s (or nothing, s < 0) of map mi to that map's list; the
+// wave's lanes may hold different maps, which are taken one map at a time.
+__device__ __forceinline__ void dirty_append_maps(const BatchMap *maps, const BatchCtl *ctl, int mi, int s)
+{
+    unsigned long long pending = __ballot(s >= 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int ml = __shfl(mi, leader, 64);
+        const bool mine = s >= 0 && mi == ml;
+        dirty_append_wave(maps[ml].v, mine ? s : -1, ctl->fs[ml].epoch);
+        pending &= ~__ballot(mine);
+    }
+}
+
+// Workers and chunks as in the per-map TSDF kernel, over the step's touched entries.
 template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCtl *ctl, int n)
 {
-    __shared__ int s_item[1];
-    __shared__ int s_slot[1];
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    constexpr int kChunk = kWidth / 8;
+    __shared__ int s_pre[kMaxBatchMaps + 1];
+    __shared__ int s_slot[kThreads / 8];
     __shared__ unsigned long long s_upd[kMaxBatchMaps];
     __shared__ int s_last;
     for (int i = threadIdx.x; i < kMaxBatchMaps; i += kThreads) s_upd[i] = 0;
-    __syncthreads();
-    const int total = ctl->pre_t[n];
-    const int lane = threadIdx.x & 63;
-    // kSched 0: the workgroup takes one item at a time; 1: each wave takes its own
-    for (;;) {
-        int item = 0;
-        if (kSched == 0) {
-            if (threadIdx.x == 0) s_item[0] = (int)atomicAdd(&ctl->queue[0], 1u);
-            __syncthreads();
-            item = s_item[0];
-        } else {
-            if (lane == 0) item = (int)atomicAdd(&ctl->queue[0], 1u);
-            item = __shfl(item, 0, 64);
+    load_prefix(s_pre, ctl->pre_t, n);
+    const int total = s_pre[n];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rank = kSched == 0 ? (int)threadIdx.x : lane;
+    const int first = kSched == 0 ? (int)blockIdx.x : (int)blockIdx.x * (kThreads / 64) + wave;
+    const int stride = kSched == 0 ? (int)gridDim.x : (int)gridDim.x * (kThreads / 64);
+    for (int base = first; base < total; base += kChunk * stride) {
+        int my_slot = -1;
+        const int ic = base + rank * stride;
+        if (rank < kChunk && ic < total) {
+            const int mi = find_map(s_pre, n, ic);
+            const int e = ic - s_pre[mi];
+            my_slot = commit_entry(maps[mi].v, maps[mi].f, ctl->fs[mi], e, maps[mi].f.tk_key[e], maps[mi].frame_id);
         }
-        if (item >= total) break;
-        const int mi = find_map(ctl->pre_t, n, item);
-        const int e = item - ctl->pre_t[mi];
-        const BatchMap &B = maps[mi];
-        const FrameState fs = frame_state(B.v, B.f);
-        const unsigned long long key = B.f.tk_key[e];
-        int slot = 0;
         if (kSched == 0) {
-            if (threadIdx.x == 0) s_slot[0] = commit_entry(B.v, B.f, fs, e, key, B.frame_id);
+            if (rank < kChunk) s_slot[rank] = my_slot;
             __syncthreads();
-            slot = s_slot[0];
-        } else {
-            if (lane == 0) slot = commit_entry(B.v, B.f, fs, e, key, B.frame_id);
-            slot = __shfl(slot, 0, 64);
         }
-        if (fs.ok) {
-            const int3 bc = unpack_key(key);
-            const int rank = kSched == 0 ? (int)threadIdx.x : lane;
-            if (rank < 8) mark_neighbours(B.v, rank, bc, slot, fs.epoch, B.frame_id);
-            float2 *dwb = B.v.dw + (size_t)slot * kBlockVoxels;
-            unsigned long long upd = 0;
-            constexpr int kWidth = kSched == 0 ? kThreads : 64;
-#pragma unroll
-            for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
-                const int li = it * kWidth + rank;
-                bool band;
-                upd += tsdf_voxel(B.v, B.lut, B.T, B.range, dwb, bc, li, band);
-                const unsigned long long bits = __ballot(band);
-                if (lane == 0) B.f.band[(size_t)e * 8 + (li >> 6)] = bits;
+        {
+            const int i = rank >> 3;
+            const int im = base + i * stride;
+            const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
+            int s = -1, mi = 0;
+            if (im < total) {
+                mi = find_map(s_pre, n, im);
+                const int e = im - s_pre[mi];
+                if (ctl->fs[mi].ok)
+                    s = neighbour_slot(maps[mi].v, rank & 7, unpack_key(maps[mi].f.tk_key[e]), si, maps[mi].frame_id);
             }
+            dirty_append_maps(maps, ctl, mi, s);
+        }
+        for (int j = 0; j < kChunk; ++j) {
+            const int item = base + j * stride;
+            if (item >= total) break;
+            const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
+            const int mi = __builtin_amdgcn_readfirstlane(find_map(s_pre, n, item));  // uniform per worker
+            if (!ctl->fs[mi].ok) continue;
+            const BatchMap &B = maps[mi];
+            const int e = item - s_pre[mi];
+            unsigned long long upd = tsdf_block<kWidth>(B.v, B.f, B.lut, B.T, B.range, e, B.f.tk_key[e], slot, rank);
             upd = wave_sum_u64(upd);
             if (lane == 0 && upd) atomicAdd(&s_upd[mi], upd);
         }
@@ -145,8 +167,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
         }
         ctl->pre_l[n] = acc_l;
         ctl->pre_d[n] = acc_d;
-        ctl->queue[1] = 0;
-        ctl->queue[2] = 0;
         ctl->done[1] = 0;
     }
 }
@@ -158,32 +178,23 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
 template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_batch_labels(BatchMap *maps, BatchCtl *ctl, int n)
 {
-    __shared__ int s_item[1];
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ unsigned long long s_votes[kMaxBatchMaps];
     for (int i = threadIdx.x; i < kMaxBatchMaps; i += kThreads) s_votes[i] = 0;
-    __syncthreads();
-    const int total = ctl->pre_l[n];
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        int item = 0;
-        if (kSched == 0) {
-            if (threadIdx.x == 0) s_item[0] = (int)atomicAdd(&ctl->queue[1], 1u);
-            __syncthreads();
-            item = s_item[0];
-            __syncthreads();  // s_item is rewritten by the next take
-        } else {
-            if (lane == 0) item = (int)atomicAdd(&ctl->queue[1], 1u);
-            item = __shfl(item, 0, 64);
-        }
-        if (item >= total) break;
-        const int mi = find_map(ctl->pre_l, n, item);
-        const int e = item - ctl->pre_l[mi];
+    load_prefix(s_pre, ctl->pre_l, n);
+    const int total = s_pre[n];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rank = kSched == 0 ? (int)threadIdx.x : lane;
+    const int first = kSched == 0 ? (int)blockIdx.x : (int)blockIdx.x * (kThreads / 64) + wave;
+    const int stride = kSched == 0 ? (int)gridDim.x : (int)gridDim.x * (kThreads / 64);
+    for (int item = first; item < total; item += stride) {
+        const int mi = __builtin_amdgcn_readfirstlane(find_map(s_pre, n, item));  // uniform per worker
         const BatchMap &B = maps[mi];
         if (B.cams.n == 0) continue;
+        const int e = item - s_pre[mi];
         const int slot = B.f.tk_slot[e];
         const int3 bc = unpack_key(B.f.tk_key[e]);
-        constexpr int kWidth = kSched == 0 ? kThreads : 64;
-        const int rank = kSched == 0 ? (int)threadIdx.x : lane;
         unsigned long long v = 0;
 #pragma unroll
         for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
@@ -207,18 +218,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_labels(BatchMap *maps, Batch
 __global__ __launch_bounds__(kThreads) void k_batch_mesh(BatchMap *maps, BatchCtl *ctl, int n)
 {
     __shared__ MeshLds S;
-    __shared__ int s_item;
+    __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ int s_last;
-    const int total = ctl->pre_d[n];
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&ctl->queue[2], 1u);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
-        if (item >= total) break;
-        const int mi = find_map(ctl->pre_d, n, item);
+    load_prefix(s_pre, ctl->pre_d, n);
+    const int total = s_pre[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int mi = find_map(s_pre, n, item);
         const BatchMap &B = maps[mi];
-        mesh_block(B.v, B.v.dirty_list[item - ctl->pre_d[mi]], B.out, &B.v.ctr->tris[B.parity], S);
+        mesh_block(B.v, B.v.dirty_list[item - s_pre[mi]], B.out, &B.v.ctr->tris[B.parity], S);
     }
     if (last_of_grid(&ctl->done[3], &s_last) && threadIdx.x == 0) {
         for (int m = 0; m < n; ++m) {

@@ -71,50 +71,50 @@ hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lu
 
 // ---------------------------------------------------------------------------------
 // TSDF integration over the touched blocks (grid-stride); the last workgroup closes the
-// frame.  kSched 0: one workgroup per block (two voxels per thread); 1: one wavefront per
-// block (eight voxels per lane, four blocks in flight per workgroup).
+// frame.  A worker is a workgroup (kSched 0, two voxels per thread) or a wavefront
+// (kSched 1, eight voxels per lane, four workers per workgroup).  A worker takes its
+// entries a chunk at a time: the chunk's commits run on one lane each and its neighbour
+// marks on eight lanes each, all at once, before the voxels of each entry in turn.
 // ---------------------------------------------------------------------------------
 
 template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, LidarLUT L, Pose T,
                                                   const float *__restrict__ range, uint32_t frame_id)
 {
-    __shared__ int s_slot;
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    constexpr int kChunk = kWidth / 8;  // entries per chunk: eight marking lanes each
+    __shared__ int s_slot[kThreads / 8];
     __shared__ int s_last;
     __shared__ unsigned long long s_sum[kThreads / 64];
     const FrameState fs = frame_state(m, f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int kWidth = kSched == 0 ? kThreads : 64;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int first = kSched == 0 ? (int)blockIdx.x : (int)blockIdx.x * (kThreads / 64) + wave;
     const int stride = kSched == 0 ? (int)gridDim.x : (int)gridDim.x * (kThreads / 64);
     unsigned long long my_updates = 0;
-    for (int e = first; e < fs.n_list; e += stride) {
-        const unsigned long long key = f.tk_key[e];
-        int slot;
+    for (int base = first; base < fs.n_list; base += kChunk * stride) {
+        int my_slot = -1;  // lane i < kChunk commits entry base + i * stride
+        const int ec = base + rank * stride;
+        if (rank < kChunk && ec < fs.n_list) my_slot = commit_entry(m, f, fs, ec, f.tk_key[ec], frame_id);
         if (kSched == 0) {
-            if (threadIdx.x == 0) s_slot = commit_entry(m, f, fs, e, key, frame_id);
+            if (rank < kChunk) s_slot[rank] = my_slot;
             __syncthreads();
-            slot = s_slot;
-        } else {
-            slot = 0;
-            if (lane == 0) slot = commit_entry(m, f, fs, e, key, frame_id);
-            slot = __shfl(slot, 0, 64);
         }
         if (fs.ok) {
-            const int3 bc = unpack_key(key);
-            if (rank < 8) mark_neighbours(m, rank, bc, slot, fs.epoch, frame_id);
-            float2 *dwb = m.dw + (size_t)slot * kBlockVoxels;
-#pragma unroll
-            for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
-                const int li = it * kWidth + rank;
-                bool band;
-                my_updates += tsdf_voxel(m, L, T, range, dwb, bc, li, band);
-                const unsigned long long bits = __ballot(band);
-                if (lane == 0) f.band[(size_t)e * 8 + (li >> 6)] = bits;
+            const int i = rank >> 3;  // lane r marks neighbour r % 8 of entry r / 8
+            const int em = base + i * stride;
+            const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
+            int s = -1;
+            if (em < fs.n_list) s = neighbour_slot(m, rank & 7, unpack_key(f.tk_key[em]), si, frame_id);
+            dirty_append_wave(m, s, fs.epoch);
+            for (int j = 0; j < kChunk; ++j) {
+                const int e = base + j * stride;
+                if (e >= fs.n_list) break;
+                const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
+                my_updates += tsdf_block<kWidth>(m, f, L, T, range, e, f.tk_key[e], slot, rank);
             }
         }
-        if (kSched == 0) __syncthreads();
+        if (kSched == 0) __syncthreads();  // s_slot is rewritten by the next chunk
     }
     const unsigned long long w = wave_sum_u64(my_updates);
     if (lane == 0) s_sum[wave] = w;

@@ -286,8 +286,8 @@ static int ensure_lut(map_t *m, const lidar_model *L, hipStream_t s)
         return fail(m, MAP_ERR_INVALID_ARG, "lidar: vertical field of view must stay within +-90 degrees");
     const size_t nfl = 2 * (size_t)R + 4 * (size_t)C + 2 * ((size_t)R + 1);
     std::vector<float> h(nfl);
-    float *ce = h.data(), *se = ce + R, *cp = se + R, *sp = cp + C, *bcx = sp + C, *bcy = bcx + C,
-          *brc = bcy + C, *brs = brc + R + 1;
+    // ce[R] se[R] cp[C] sp[C], then (cos, sin) pairs: bc[C], br[R + 1] (8-byte aligned)
+    float *ce = h.data(), *se = ce + R, *cp = se + R, *sp = cp + C, *bc = sp + C, *br = bc + 2 * C;
     for (int k = 0; k < R; ++k) {
         ce[k] = (float)std::cos((double)L->elev_rad[k]);
         se[k] = (float)std::sin((double)L->elev_rad[k]);
@@ -298,13 +298,13 @@ static int ensure_lut(map_t *m, const lidar_model *L, hipStream_t s)
         cp[c] = (float)std::cos(phi);
         sp[c] = (float)std::sin(phi);
         const double pb = M_PI - ((double)c - 0.5) * dphi;
-        bcx[c] = (float)std::cos(pb);
-        bcy[c] = (float)std::sin(pb);
+        bc[2 * c] = (float)std::cos(pb);
+        bc[2 * c + 1] = (float)std::sin(pb);
     }
     for (int j = 0; j <= R; ++j) {
         double eb = j == 0 ? top : (j == R ? bot : 0.5 * ((double)L->elev_rad[j - 1] + (double)L->elev_rad[j]));
-        brc[j] = (float)std::cos(eb);
-        brs[j] = (float)std::sin(eb);
+        br[2 * j] = (float)std::cos(eb);
+        br[2 * j + 1] = (float)std::sin(eb);
     }
     // the previous frame may still read the old tables
     HIP_TRY(m, hipStreamSynchronize(s));
@@ -321,14 +321,14 @@ static int ensure_lut(map_t *m, const lidar_model *L, hipStream_t s)
     lut.se = d + R;
     lut.cp = d + 2 * R;
     lut.sp = lut.cp + C;
-    lut.bcx = lut.sp + C;
-    lut.bcy = lut.bcx + C;
-    lut.brc = lut.bcy + C;
-    lut.brs = lut.brc + R + 1;
+    lut.bc = reinterpret_cast<const float2 *>(lut.sp + C);
+    lut.br = lut.bc + C;
     lut.rows = R;
     lut.cols = C;
     lut.r_max = L->r_max;
     lut.cols_over_2pi = (float)((double)C / (2.0 * M_PI));
+    lut.el_top = (float)top;
+    lut.rows_over_fov = (float)((double)R / (top - bot));
     m->lut_rows = R;
     m->lut_cols = C;
     m->lut_rmax = L->r_max;
