@@ -179,7 +179,7 @@ typedef struct {
 
 int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out);
 /* schedule: 0 = one workgroup per touched block, 1 = one wavefront per touched block;
- * grid: workgroups of the persistent phases (64..65536); use_graph: capture each step
+ * grid: workgroups of the persistent phases (64..4096); use_graph: capture each step
  * shape once in a hipGraph and replay it. */
 int map_batch_configure(map_batch_t *batch, int32_t schedule, int32_t grid, int32_t use_graph);
 int map_batch_step(map_batch_t *batch, const map_batch_item *items, int32_t n_items, int64_t *n_tris,

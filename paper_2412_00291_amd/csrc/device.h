@@ -331,9 +331,24 @@ __device__ __forceinline__ T coherent_load(T *p)
 // unused) have completed, so a following ticket atomic is performed after them.
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Frame state after allocation (device-coherent loads: the counters were last written by
-// atomics).
+// Frame state after allocation, read by a later launch (plain loads: the counters'
+// last atomic updates were performed before that launch began).
 __device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameView &f)
+{
+    const Counters *c = m.ctr;
+    const unsigned long long tn = c->touched_new;
+    FrameState s;
+    const int n_touched = (int)(tn & 0xFFFFFFFFull);
+    s.n_new = (int)(tn >> 32);
+    s.used = c->pool_used;
+    s.epoch = c->dirty_epoch;
+    s.ok = c->overflow == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
+    s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
+    return s;
+}
+
+// The same, read in the launch whose atomics wrote the counters (device-coherent loads).
+__device__ __forceinline__ FrameState frame_state_coherent(const MapView &m, const FrameView &f)
 {
     Counters *c = m.ctr;
     const unsigned long long tn = coherent_load(&c->touched_new);
@@ -345,6 +360,39 @@ __device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameV
     s.ok = coherent_load(&c->overflow) == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
     s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
     return s;
+}
+
+// ---------------------------------------------------------------------------------
+// spread counters and hierarchical tickets (no address takes more than ~64 atomics)
+// ---------------------------------------------------------------------------------
+
+__device__ __forceinline__ void spread_add(Spread &s, unsigned long long v)
+{
+    atomicAdd(&s.v[(blockIdx.x % kLeaves) * kLeafPad], v);
+}
+
+// Sum and clear a spread counter: called by one whole wavefront (lane l takes leaf l);
+// every lane gets the sum.  Its caller is the counter's only user at that time.
+__device__ __forceinline__ unsigned long long spread_take_wave(Spread &s)
+{
+    const int lane = threadIdx.x & 63;
+    return wave_sum_u64(atomicExch(&s.v[lane * kLeafPad], 0ull));
+}
+
+// One thread per workgroup, after the workgroup's work: true in exactly one workgroup,
+// the last to arrive, which also resets the ticket for the next launch.
+__device__ __forceinline__ bool ticket_arrive(Ticket &t)
+{
+    const unsigned G = gridDim.x;
+    const unsigned leaves = G < (unsigned)kLeaves ? G : (unsigned)kLeaves;
+    const unsigned l = blockIdx.x % leaves;
+    const unsigned long long expect = (G - l + leaves - 1) / leaves;  // workgroups of leaf l
+    wait_memory();  // this workgroup's earlier memory operations complete first
+    if (atomicAdd(&t.leaf[l * kLeafPad], 1ull) + 1ull != expect) return false;
+    if (atomicAdd(&t.root[0], 1ull) + 1ull != leaves) return false;
+    for (unsigned i = 0; i < leaves; ++i) atomicExch(&t.leaf[i * kLeafPad], 0ull);
+    atomicExch(&t.root[0], 0ull);
+    return true;
 }
 
 // Insert a new block: claim the slot with a CAS on the key, then write the pool slot and
@@ -379,23 +427,6 @@ __device__ __forceinline__ int hash_find_old(const MapView &m, unsigned long lon
         i = (i + 1) & m.hmask;
     }
     return -1;
-}
-
-// Mark slot s dirty (s < 0: nothing) and append it to the dirty list if this frame had
-// not marked it yet, with one list reservation per wavefront.  Every lane of the wave
-// calls it, all with the same map.
-__device__ __forceinline__ void dirty_append_wave(const MapView &m, int s, uint32_t epoch)
-{
-    bool app = false;
-    if (s >= 0) app = atomicExch(&m.dirty_flag[s], epoch) != epoch;
-    const unsigned long long mask = __ballot(app);
-    if (mask == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&m.ctr->n_dirty, __popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (app) m.dirty_list[base + __popcll(mask & ((1ull << lane) - 1ull))] = s;
 }
 
 // Commit of touched entry e by one thread: clear its frame-set slot, and give a new block
@@ -480,18 +511,19 @@ __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const
 }
 
 // Close the frame (one thread, after every worker of the TSDF phase has finished):
-// commit the pool size, record the frame's counts, reset the per-frame counters.
-__device__ __forceinline__ void close_frame(const MapView &m, const FrameState &fs)
+// commit the pool size, record the frame's counts, reset the per-frame counters.  The
+// caller has taken the frame's update count from its spread counter and cleared the
+// votes of the previous frame.
+__device__ __forceinline__ void close_frame(const MapView &m, const FrameState &fs, unsigned long long updates)
 {
     Counters *c = m.ctr;
-    const unsigned long long upd = atomicAdd(&c->updates, 0ull);
     if (fs.ok) {
         c->pool_used = fs.used + fs.n_new;
         c->frames += 1;
         c->frame_ok = 1;
         c->last_touched = fs.n_list;
         c->last_new = fs.n_new;
-        c->last_updates = upd;
+        c->last_updates = updates;
     } else {
         c->frame_ok = 0;
         c->status = -2;  // MAP_ERR_CAPACITY, reported by the next synchronising call
@@ -500,9 +532,16 @@ __device__ __forceinline__ void close_frame(const MapView &m, const FrameState &
         c->last_updates = 0;
     }
     c->touched_new = 0;
-    c->updates = 0;
-    c->votes = 0;
     c->overflow = 0;
+}
+
+// The last workgroup's part of closing a map's frame: wave 0 takes the update count and
+// clears the votes, then closes the frame.
+__device__ __forceinline__ void close_frame_wave(const MapView &m, const FrameState &fs)
+{
+    const unsigned long long upd = spread_take_wave(m.sync->updates);
+    (void)spread_take_wave(m.sync->votes);
+    if ((threadIdx.x & 63) == 0) close_frame(m, fs, upd);
 }
 
 // ---------------------------------------------------------------------------------

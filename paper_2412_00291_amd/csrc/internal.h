@@ -17,21 +17,40 @@ struct Counters {
     unsigned long long touched_new; // this frame: low 32 bits |T_k| entries, high 32 bits new ones
     int32_t pool_used;   // allocated blocks
     int32_t frame_ok;    // 1 if the last frame was accepted
-    int32_t n_dirty;     // entries of the dirty list
-    uint32_t dirty_epoch;
+    uint32_t dirty_epoch;  // a block is dirty when its flag holds this value
+    uint32_t mesh_epoch;   // epoch being meshed by the current extraction
     int32_t status;      // deferred error (MAP_ERR_CAPACITY) until read by the host
     int32_t frames;      // accepted frames
-    unsigned long long updates;     // U_k being accumulated
-    unsigned long long votes;       // label votes since the last LiDAR frame
-    unsigned long long tris[2];     // triangles of an extraction (parity-buffered)
+    unsigned long long mesh_tris;   // triangles of the last extraction
     unsigned long long mesh_blocks; // blocks of the last extraction
     unsigned long long last_updates;
     int32_t last_touched;  // |T_k| of the last accepted frame (labels read it)
     int32_t last_new;
     int32_t overflow;      // touched list overflow (cannot happen with the sizing rule)
-    uint32_t tsdf_done;    // workgroup tickets
-    uint32_t mesh_done;
     int32_t pad;
+};
+
+// Same-address device atomics are serialised (about 12 ns apart on gfx950), so a value
+// that every workgroup adds to is spread over kLeaves counters 128 bytes apart (a
+// workgroup adds to leaf blockIdx % kLeaves) and summed by its single reader.
+constexpr int kLeaves = 64;
+constexpr int kLeafPad = 16;  // 64-bit words per leaf
+struct Spread {
+    unsigned long long v[kLeaves * kLeafPad];
+};
+
+// Hierarchical "last workgroup" ticket: a workgroup arrives at its leaf; the one that
+// completes a leaf arrives at the root; the one that completes the root is last.
+struct Ticket {
+    unsigned long long leaf[kLeaves * kLeafPad];
+    unsigned long long root[kLeafPad];
+};
+
+// Per-map synchronisation state (device, zero-initialised).
+struct SyncState {
+    Ticket tsdf;     // TSDF phase: the last workgroup closes the frame
+    Spread updates;  // U_k being accumulated
+    Spread votes;    // label votes since the last LiDAR frame
 };
 
 // Block pool, hash and dirty set.
@@ -44,12 +63,23 @@ struct MapView {
     int32_t *hvals;           // [hmask + 1]
     uint32_t *hframe;         // [hmask + 1] integration call that inserted the key (~0: none)
     uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
-    int32_t *dirty_list;      // [max_blocks]
+    uint16_t *mesh_cnt;       // [max_blocks] triangles of a block in the current extraction
     Counters *ctr;
+    SyncState *sync;
     uint32_t hmask;
     int32_t n_classes;
     int32_t max_blocks;
     float nu, tau;
+};
+
+constexpr int kMaxMeshGrid = 4096;  // workgroups of a meshing pass (and of a batched phase)
+
+// Scratch of one extraction: per-workgroup triangle and block counts of the counting
+// pass, and the output offsets of the emitting pass (per map of a batch: [grid][maps]).
+struct MeshScan {
+    long long *wg_tris;
+    int32_t *wg_blocks;
+    long long *wg_off;
 };
 
 // Per-frame scratch: frame set (de-duplication of the frame's blocks) and touched list.
@@ -157,7 +187,6 @@ struct BatchMap {  // one map's frame in a batched step (device array, refreshed
     CameraSet cams;
     MeshOut out;
     int32_t tile0, tiles;  // this map's allocation tiles in the step's tile space
-    int32_t parity;        // this map's extraction parity
     uint32_t frame_id;     // this map's integration call number
 };
 
@@ -169,16 +198,20 @@ struct FrameState {
 };
 
 struct BatchCtl {  // device
-    uint32_t done[4];   // workgroup tickets per phase
     FrameState fs[kMaxBatchMaps];      // per-map frame state after allocation
     int32_t pre_t[kMaxBatchMaps + 1];  // prefix sums over maps: touched entries
     int32_t pre_l[kMaxBatchMaps + 1];  // label entries
-    int32_t pre_d[kMaxBatchMaps + 1];  // dirty blocks
+    int32_t pre_p[kMaxBatchMaps + 1];  // mesh candidates (pool slots)
     unsigned long long tris[kMaxBatchMaps];  // triangle count per map (read back)
 };
 
-hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, int n_maps, int total_tiles, int schedule, int grid,
-                        hipStream_t s);
+struct BatchSync {  // device, zero-initialised
+    Ticket alloc;
+    Ticket tsdf;
+};
+
+hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan scan, int n_maps, int total_tiles,
+                        int schedule, int grid, hipStream_t s);
 
 hipError_t launch_init_pool(const MapView &m, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
@@ -188,8 +221,15 @@ hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut
                        const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s);
 hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int schedule, int grid,
                          hipStream_t s);
-hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int schedule, int grid,
-                       hipStream_t s);
+// Workgroups of the meshing passes: the emitting pass's grid and the counting pass's,
+// a multiple of it (each the device-resident grid of its kernel).
+struct MeshGrid {
+    int emit, count;
+};
+MeshGrid mesh_grid(int schedule);
+MeshGrid batch_mesh_grid();
+hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, int schedule,
+                       MeshGrid grid, hipStream_t s);
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
                         uint8_t *valid, hipStream_t s);
 hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,

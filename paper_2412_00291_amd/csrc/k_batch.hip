@@ -1,11 +1,11 @@
 // Batched step over many maps of uneven size: one launch per phase (allocation, TSDF,
-// labels, meshing) covers every map of the step, so a step is four launches (one graph
-// launch when captured) instead of four per map.  Each phase's items (pixel tiles,
-// touched entries, dirty blocks) are numbered across the maps by prefix sums, and the
-// grid strides over them statically; each item runs the same device body as the
-// per-map kernels, so every map ends bit-identical to its own plain calls.  The last
-// workgroup of each phase does the per-map bookkeeping and lays out the next phase's
-// prefix sums.
+// labels, meshing in three passes) covers every map of the step, so a step is six
+// launches (one graph launch when captured) instead of six per map.  Each phase's items
+// (pixel tiles, touched entries, mesh candidates) are numbered across the maps by prefix
+// sums, and the grid strides over them statically; each item runs the same device body
+// as the per-map kernels, so every map ends bit-identical to its own plain calls.  The
+// last workgroup of the allocation and TSDF phases (hierarchical tickets) does the
+// per-map bookkeeping and lays out the next phase's prefix sums.
 //
 // Schedules for the TSDF and label phases: 0 = one workgroup per touched block (two
 // voxels per thread), 1 = one wavefront per touched block (eight voxels per lane, four
@@ -25,21 +25,11 @@ __device__ __forceinline__ int find_map(const int32_t *pre, int n, int i)
     return lo;
 }
 
-__device__ __forceinline__ bool last_of_grid(uint32_t *ticket, int *s_last)
-{
-    if (threadIdx.x == 0) {
-        wait_memory();  // this workgroup's atomics land before its ticket
-        *s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    return *s_last;
-}
-
 // ---------------------------------------------------------------------------------
 // allocation: the step's pixel tiles, each tile inside one map
 // ---------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_batch_alloc(BatchMap *maps, BatchCtl *ctl, int n)
+__global__ __launch_bounds__(kThreads) void k_batch_alloc(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, int n)
 {
     __shared__ unsigned long long lk[kLdsKeys];
     __shared__ int s_tmp[kThreads / 64];
@@ -54,16 +44,17 @@ __global__ __launch_bounds__(kThreads) void k_batch_alloc(BatchMap *maps, BatchC
     if (pix < B.lut.rows * B.lut.cols) alloc_pixel(lk, B.v, B.f, B.lut, B.T, B.range, pix);
     __syncthreads();
     alloc_flush(lk, s_tmp, &s_base, B.v, B.f);
-    if (last_of_grid(&ctl->done[0], &s_last) && threadIdx.x == 0) {
+    if (threadIdx.x == 0) s_last = ticket_arrive(sync->alloc);
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
         int acc = 0;
         for (int m = 0; m < n; ++m) {
-            const FrameState fs = frame_state(maps[m].v, maps[m].f);
+            const FrameState fs = frame_state_coherent(maps[m].v, maps[m].f);
             ctl->fs[m] = fs;
             ctl->pre_t[m] = acc;
             acc += fs.n_list;
         }
         ctl->pre_t[n] = acc;
-        ctl->done[0] = 0;
     }
 }
 
@@ -78,23 +69,9 @@ __device__ __forceinline__ void load_prefix(int *dst, const int32_t *src, int n)
     __syncthreads();
 }
 
-// Append this lane's dirty slot s (or nothing, s < 0) of map mi to that map's list; the
-// wave's lanes may hold different maps, which are taken one map at a time.
-__device__ __forceinline__ void dirty_append_maps(const BatchMap *maps, const BatchCtl *ctl, int mi, int s)
-{
-    unsigned long long pending = __ballot(s >= 0);
-    while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const int ml = __shfl(mi, leader, 64);
-        const bool mine = s >= 0 && mi == ml;
-        dirty_append_wave(maps[ml].v, mine ? s : -1, ctl->fs[ml].epoch);
-        pending &= ~__ballot(mine);
-    }
-}
-
 // Workers and chunks as in the per-map TSDF kernel, over the step's touched entries.
 template <int kSched>
-__global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCtl *ctl, int n)
+__global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, int n)
 {
     constexpr int kWidth = kSched == 0 ? kThreads : 64;
     constexpr int kChunk = kWidth / 8;
@@ -125,14 +102,16 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
             const int i = rank >> 3;
             const int im = base + i * stride;
             const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
-            int s = -1, mi = 0;
             if (im < total) {
-                mi = find_map(s_pre, n, im);
+                const int mi = find_map(s_pre, n, im);
                 const int e = im - s_pre[mi];
-                if (ctl->fs[mi].ok)
-                    s = neighbour_slot(maps[mi].v, rank & 7, unpack_key(maps[mi].f.tk_key[e]), si, maps[mi].frame_id);
+                const FrameState &fs = ctl->fs[mi];
+                if (fs.ok) {
+                    const MapView &v = maps[mi].v;
+                    const int s = neighbour_slot(v, rank & 7, unpack_key(maps[mi].f.tk_key[e]), si, maps[mi].frame_id);
+                    if (s >= 0) v.dirty_flag[s] = fs.epoch;
+                }
             }
-            dirty_append_maps(maps, ctl, mi, s);
         }
         for (int j = 0; j < kChunk; ++j) {
             const int item = base + j * stride;
@@ -150,24 +129,22 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
     }
     __syncthreads();
     for (int m = threadIdx.x; m < n; m += kThreads)
-        if (s_upd[m]) atomicAdd(&maps[m].v.ctr->updates, s_upd[m]);
-    if (last_of_grid(&ctl->done[1], &s_last) && threadIdx.x == 0) {
-        int acc_l = 0, acc_d = 0;
+        if (s_upd[m]) spread_add(maps[m].v.sync->updates, s_upd[m]);
+    if (threadIdx.x == 0) s_last = ticket_arrive(sync->tsdf);
+    __syncthreads();
+    if (!s_last) return;
+    for (int m = wave; m < n; m += kThreads / 64) close_frame_wave(maps[m].v, ctl->fs[m]);
+    if (threadIdx.x == 0) {
+        int acc_l = 0, acc_p = 0;
         for (int m = 0; m < n; ++m) {
-            const BatchMap &B = maps[m];
-            close_frame(B.v, frame_state(B.v, B.f));
+            const FrameState &fs = ctl->fs[m];
             ctl->pre_l[m] = acc_l;
-            acc_l += B.v.ctr->last_touched;
-            ctl->pre_d[m] = acc_d;
-            const int nd = coherent_load(&B.v.ctr->n_dirty);
-            acc_d += nd;
-            B.v.ctr->mesh_blocks = (unsigned long long)nd;
-            B.v.ctr->tris[B.parity] = 0;
-            B.v.ctr->tris[1 - B.parity] = 0;
+            acc_l += fs.ok ? fs.n_list : 0;
+            ctl->pre_p[m] = acc_p;
+            acc_p += fs.ok ? fs.used + fs.n_new : fs.used;
         }
         ctl->pre_l[n] = acc_l;
-        ctl->pre_d[n] = acc_d;
-        ctl->done[1] = 0;
+        ctl->pre_p[n] = acc_p;
     }
 }
 
@@ -208,49 +185,192 @@ __global__ __launch_bounds__(kThreads) void k_batch_labels(BatchMap *maps, Batch
     }
     __syncthreads();
     for (int m = threadIdx.x; m < n; m += kThreads)
-        if (s_votes[m]) atomicAdd(&maps[m].v.ctr->votes, s_votes[m]);
+        if (s_votes[m]) spread_add(maps[m].v.sync->votes, s_votes[m]);
 }
 
 // ---------------------------------------------------------------------------------
-// meshing phase: one workgroup per dirty block
+// meshing phase: counting pass, per-map scans, emitting pass (one workgroup per block)
 // ---------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_batch_mesh(BatchMap *maps, BatchCtl *ctl, int n)
+// One iteration's candidates of this workgroup over the step's concatenated pool slots
+// (map m's slots are items pre[m] .. pre[m+1]-1), compacted into S.list as item numbers;
+// dealt out as in the per-map passes.  Returns their number, or -1 past the end.
+__device__ __forceinline__ int batch_candidates(const BatchMap *maps, const int *s_pre, const uint32_t *s_epoch,
+                                                int n, int it, bool need_tris, MeshSmem<0> &S)
 {
-    __shared__ MeshLds S;
-    __shared__ int s_pre[kMaxBatchMaps + 1];
-    __shared__ int s_last;
-    load_prefix(s_pre, ctl->pre_d, n);
     const int total = s_pre[n];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int mi = find_map(s_pre, n, item);
-        const BatchMap &B = maps[mi];
-        mesh_block(B.v, B.v.dirty_list[item - s_pre[mi]], B.out, &B.v.ctr->tris[B.parity], S);
+    if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= total) return -1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long item = ((long long)it * kThreads + threadIdx.x) * gridDim.x + blockIdx.x;
+    bool take = false;
+    if (item < total) {
+        const int mi = find_map(s_pre, n, (int)item);
+        const MapView &v = maps[mi].v;
+        take = v.dirty_flag[item - s_pre[mi]] == s_epoch[mi];
+        if (need_tris && take) take = v.mesh_cnt[item - s_pre[mi]] != 0;
     }
-    if (last_of_grid(&ctl->done[3], &s_last) && threadIdx.x == 0) {
-        for (int m = 0; m < n; ++m) {
-            const BatchMap &B = maps[m];
-            unsigned long long *tris = &B.v.ctr->tris[B.parity];
-            close_extraction(B.v, 0, tris, B.out.cap);
-            ctl->tris[m] = atomicAdd(tris, 0ull);
+    const unsigned long long bal = __ballot(take);
+    if (lane == 0) S.wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, cnt = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const int c = S.wcnt[w];
+        off += w < wave ? c : 0;
+        cnt += c;
+    }
+    if (take) S.list[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)item;
+    __syncthreads();
+    return cnt;
+}
+
+// Map, coordinates and neighbour slots of list entries j0 .. j0 + nb - 1 (as
+// mesh_batch_lookup, the map resolved per entry).
+__device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_pre, int n, MeshSmem<0> &S, int j0,
+                                             int nb)
+{
+    const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
+    if (jb < nb) {
+        const int item = S.list[j0 + jb];
+        const int mi = find_map(s_pre, n, item);
+        const MapView &v = maps[mi].v;
+        const int slot = item - s_pre[mi];
+        const int4 bc = v.coords[slot];
+        if (e == 0) {
+            S.bcs[jb] = bc;
+            S.mis[jb] = mi;
         }
-        ctl->done[3] = 0;
+        S.nbs[jb][e] = e == 0 ? slot : hash_find(v, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
+{
+    __shared__ MeshSmem<0> S;
+    __shared__ int s_pre[kMaxBatchMaps + 1];
+    __shared__ uint32_t s_epoch[kMaxBatchMaps];
+    __shared__ long long s_tris[kMaxBatchMaps];
+    __shared__ int s_blocks[kMaxBatchMaps];
+    for (int m = threadIdx.x; m < n; m += kThreads) {
+        s_epoch[m] = maps[m].v.ctr->dirty_epoch;
+        s_tris[m] = 0;
+        s_blocks[m] = 0;
+    }
+    load_prefix(s_pre, ctl->pre_p, n);
+    mesh_tables(S);
+    unsigned counts;
+    for (int it = 0;; ++it) {
+        const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, false, S);
+        if (cnt < 0) break;
+        for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
+            const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
+            batch_lookup(maps, s_pre, n, S, j0, nb);
+            for (int j = 0; j < nb; ++j) {
+                const int mi = S.mis[j];
+                mesh_stage<0>(maps[mi].v, S.nbs[j], S.h[0], threadIdx.x);
+                const unsigned long long t =
+                    wave_sum_u64((unsigned long long)mesh_classify<0>(S.h[0], S.ntri, threadIdx.x, nullptr, &counts));
+                if ((threadIdx.x & 63) == 0) S.rcnt[threadIdx.x >> 6] = (long long)t;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    long long tot = 0;
+                    for (int w = 0; w < kThreads / 64; ++w) tot += S.rcnt[w];
+                    maps[mi].v.mesh_cnt[S.nbs[j][0]] = (uint16_t)tot;
+                    s_tris[mi] += tot;
+                    s_blocks[mi] += 1;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+    for (int m = threadIdx.x; m < n; m += kThreads) {
+        scan.wg_tris[(size_t)blockIdx.x * n + m] = s_tris[m];
+        scan.wg_blocks[(size_t)blockIdx.x * n + m] = s_blocks[m];
     }
 }
 
-hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, int n_maps, int total_tiles, int schedule, int grid,
-                        hipStream_t s)
+// One workgroup per map: that map's offsets over the counting pass's workgroups.
+__global__ __launch_bounds__(kThreads) void k_batch_mesh_scan(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n, int G,
+                                                              int k)
 {
-    if (total_tiles > 0) hipLaunchKernelGGL(k_batch_alloc, dim3(total_tiles), dim3(kThreads), 0, s, maps, ctl, n_maps);
-    else return hipErrorInvalidValue;
+    const int m = blockIdx.x;
+    const BatchMap &B = maps[m];
+    mesh_scan_map(B.v, 0, scan.wg_tris + m, scan.wg_blocks + m, scan.wg_off + m, G, k, n, B.out.cap, &ctl->tris[m]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
+{
+    __shared__ MeshSmem<0> S;
+    __shared__ MeshStage st;
+    __shared__ int s_pre[kMaxBatchMaps + 1];
+    __shared__ uint32_t s_epoch[kMaxBatchMaps];
+    __shared__ long long s_next[kMaxBatchMaps];
+    for (int m = threadIdx.x; m < n; m += kThreads) {
+        s_epoch[m] = maps[m].v.ctr->mesh_epoch;
+        s_next[m] = scan.wg_off[(size_t)blockIdx.x * n + m];
+    }
+    load_prefix(s_pre, ctl->pre_p, n);
+    mesh_tables(S);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned counts;
+    for (int it = 0;; ++it) {
+        const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, true, S);
+        if (cnt < 0) break;
+        for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
+            const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
+            batch_lookup(maps, s_pre, n, S, j0, nb);
+            for (int j = 0; j < nb; ++j) {
+                const int mi = S.mis[j];
+                const BatchMap &B = maps[mi];
+                mesh_stage<0>(B.v, S.nbs[j], S.h[0], threadIdx.x);
+                if (threadIdx.x == 0) S.rbc[0] = S.bcs[j];
+                const int mine = mesh_classify<0>(S.h[0], S.ntri, threadIdx.x, S.ccase[0], &counts);
+                const int incl = wave_scan_incl(mine);
+                if (lane == 63) S.rcnt[wave] = incl;
+                __syncthreads();
+                int woff = 0, tot = 0;
+#pragma unroll
+                for (int w = 0; w < kThreads / 64; ++w) {
+                    const int c = (int)S.rcnt[w];
+                    woff += w < wave ? c : 0;
+                    tot += c;
+                }
+                const long long r0 = s_next[mi];
+                mesh_round_out<0>(B.v, S, st, true, 0, threadIdx.x, counts, woff + incl - mine, mine, tot, r0, B.out);
+                if (threadIdx.x == 0) s_next[mi] = r0 + tot;
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+MeshGrid batch_mesh_grid()
+{
+    static MeshGrid cached = {0, 0};
+    if (!cached.emit) cached = resident_grids(k_batch_mesh_count, k_batch_mesh_emit);
+    return cached;
+}
+
+hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan scan, int n_maps, int total_tiles,
+                        int schedule, int grid, hipStream_t s)
+{
+    const MeshGrid mg = batch_mesh_grid();
+    if (total_tiles < 1 || grid < 1 || grid > kMaxMeshGrid) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_alloc, dim3(total_tiles), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
     if (schedule == 0) {
-        hipLaunchKernelGGL(k_batch_tsdf<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
+        hipLaunchKernelGGL(k_batch_tsdf<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
         hipLaunchKernelGGL(k_batch_labels<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
     } else {
-        hipLaunchKernelGGL(k_batch_tsdf<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
+        hipLaunchKernelGGL(k_batch_tsdf<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
         hipLaunchKernelGGL(k_batch_labels<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
     }
-    hipLaunchKernelGGL(k_batch_mesh, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
+    hipLaunchKernelGGL(k_batch_mesh_count, dim3(mg.count), dim3(kThreads), 0, s, maps, ctl, scan, n_maps);
+    hipLaunchKernelGGL(k_batch_mesh_scan, dim3(n_maps), dim3(kThreads), 0, s, maps, ctl, scan, n_maps, mg.emit,
+                       mg.count / mg.emit);
+    hipLaunchKernelGGL(k_batch_mesh_emit, dim3(mg.emit), dim3(kThreads), 0, s, maps, ctl, scan, n_maps);
     return hipGetLastError();
 }
 

@@ -70,8 +70,8 @@ hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lu
 }
 
 // ---------------------------------------------------------------------------------
-// TSDF integration over the touched blocks (grid-stride); the last workgroup closes the
-// frame.  A worker is a workgroup (kSched 0, two voxels per thread) or a wavefront
+// TSDF integration over the touched blocks (grid-stride); the last workgroup (by a
+// hierarchical ticket) closes the frame.  A worker is a workgroup (kSched 0, two voxels per thread) or a wavefront
 // (kSched 1, eight voxels per lane, four workers per workgroup).  A worker takes its
 // entries a chunk at a time: the chunk's commits run on one lane each and its neighbour
 // marks on eight lanes each, all at once, before the voxels of each entry in turn.
@@ -104,9 +104,10 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
             const int i = rank >> 3;  // lane r marks neighbour r % 8 of entry r / 8
             const int em = base + i * stride;
             const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
-            int s = -1;
-            if (em < fs.n_list) s = neighbour_slot(m, rank & 7, unpack_key(f.tk_key[em]), si, frame_id);
-            dirty_append_wave(m, s, fs.epoch);
+            if (em < fs.n_list) {
+                const int s = neighbour_slot(m, rank & 7, unpack_key(f.tk_key[em]), si, frame_id);
+                if (s >= 0) m.dirty_flag[s] = fs.epoch;
+            }
             for (int j = 0; j < kChunk; ++j) {
                 const int e = base + j * stride;
                 if (e >= fs.n_list) break;
@@ -122,15 +123,11 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int i = 0; i < kThreads / 64; ++i) t += s_sum[i];
-        if (t) atomicAdd(&m.ctr->updates, t);
-        wait_memory();  // the update count lands before the ticket
-        s_last = atomicAdd(&m.ctr->tsdf_done, 1u) == gridDim.x - 1;
+        if (t) spread_add(m.sync->updates, t);
+        s_last = ticket_arrive(m.sync->tsdf);
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        close_frame(m, fs);
-        m.ctr->tsdf_done = 0;
-    }
+    if (s_last && wave == 0) close_frame_wave(m, fs);
 }
 
 hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
@@ -174,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int i = 0; i < kThreads / 64; ++i) t += s_sum[i];
-        if (t) atomicAdd(&m.ctr->votes, t);
+        if (t) spread_add(m.sync->votes, t);
     }
 }
 

@@ -1,52 +1,59 @@
-// Marching cubes over the dirty (or all) blocks of one map: one workgroup per block (see
-// mesh_device.h).  The triangle counter is parity-buffered: extraction p counts into
-// tris[p] and clears tris[1 - p] (already read by the host) for the next one; the last
-// workgroup clears the dirty set when a DIRTY extraction fit in the output.
+// Marching cubes over the dirty (or all) blocks of one map, in three launches: count
+// triangles per workgroup, scan the counts (one workgroup, which also does the
+// extraction's bookkeeping), emit at the scanned offsets.  Both passes take the same
+// candidate blocks in the same order (see mesh_device.h), so the output is compact.
 #include "mesh_device.h"
 
 namespace mc {
 
 template <int kSched>
-__global__ __launch_bounds__(kThreads) void k_mesh(MapView m, int mode, int parity, MeshOut out)
+__global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, MeshScan scan)
 {
-    // kSched 0: one workgroup per block; 1: one wavefront per block (own LDS region)
-    constexpr size_t kLds = kSched == 0 ? sizeof(MeshLds) : (kThreads / 64) * sizeof(MeshLdsWave);
-    __shared__ __align__(16) char smem[kLds];
-    __shared__ int s_last;
-    MeshLds &S = *reinterpret_cast<MeshLds *>(smem);
-    MeshLdsWave *SW = reinterpret_cast<MeshLdsWave *>(smem);
-    Counters *c = m.ctr;
-    unsigned long long *tris = &c->tris[parity];
-    const int nblk = mode == 0 ? c->n_dirty : c->pool_used;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        c->mesh_blocks = (unsigned long long)nblk;
-        c->tris[1 - parity] = 0;
-    }
-    if (kSched == 0) {
-        for (int e = blockIdx.x; e < nblk; e += gridDim.x)
-            mesh_block(m, mode == 0 ? m.dirty_list[e] : e, out, tris, S);
-    } else {
-        const int wave = threadIdx.x >> 6;
-        for (int e = blockIdx.x * (kThreads / 64) + wave; e < nblk; e += gridDim.x * (kThreads / 64))
-            mesh_block_wave(m, mode == 0 ? m.dirty_list[e] : e, out, tris, SW[wave]);
-        __syncthreads();
-    }
+    __shared__ MeshSmem<kSched> S;
+    const Counters *c = m.ctr;
+    long long tris;
+    int blocks;
+    mesh_count_wg<kSched>(m, mode != 0, c->dirty_epoch, c->pool_used, S, &tris, &blocks);
     if (threadIdx.x == 0) {
-        wait_memory();  // every triangle reservation lands before the ticket
-        s_last = atomicAdd(&c->mesh_done, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        close_extraction(m, mode, tris, out.cap);
-        c->mesh_done = 0;
+        scan.wg_tris[blockIdx.x] = tris;
+        scan.wg_blocks[blockIdx.x] = blocks;
     }
 }
 
-hipError_t launch_mesh(const MapView &m, int mode, int parity, const MeshOut &out, int schedule, int grid,
-                       hipStream_t s)
+__global__ __launch_bounds__(kThreads) void k_mesh_scan(MapView m, int mode, MeshScan scan, int G, int k, long long cap)
 {
-    if (schedule == 0) hipLaunchKernelGGL(k_mesh<0>, dim3(grid), dim3(kThreads), 0, s, m, mode, parity, out);
-    else hipLaunchKernelGGL(k_mesh<1>, dim3(grid), dim3(kThreads), 0, s, m, mode, parity, out);
+    mesh_scan_map(m, mode, scan.wg_tris, scan.wg_blocks, scan.wg_off, G, k, 1, cap, nullptr);
+}
+
+template <int kSched>
+__global__ __launch_bounds__(kThreads) void k_mesh_emit(MapView m, int mode, MeshScan scan, MeshOut out)
+{
+    __shared__ MeshSmem<kSched> S;
+    __shared__ MeshStage st;
+    const Counters *c = m.ctr;
+    mesh_emit_wg<kSched>(m, mode != 0, c->mesh_epoch, c->pool_used, scan.wg_off[blockIdx.x], out, S, st);
+}
+
+MeshGrid mesh_grid(int schedule)
+{
+    static MeshGrid cached[2] = {{0, 0}, {0, 0}};
+    const int k = schedule != 0;
+    if (!cached[k].emit)
+        cached[k] = k == 0 ? resident_grids(k_mesh_count<0>, k_mesh_emit<0>) : resident_grids(k_mesh_count<1>, k_mesh_emit<1>);
+    return cached[k];
+}
+
+hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, int schedule,
+                       MeshGrid grid, hipStream_t s)
+{
+    if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
+        return hipErrorInvalidValue;
+    const int k = grid.count / grid.emit;
+    if (schedule == 0) hipLaunchKernelGGL(k_mesh_count<0>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
+    else hipLaunchKernelGGL(k_mesh_count<1>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
+    hipLaunchKernelGGL(k_mesh_scan, dim3(1), dim3(kThreads), 0, s, m, mode, scan, grid.emit, k, out.cap);
+    if (schedule == 0) hipLaunchKernelGGL(k_mesh_emit<0>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
+    else hipLaunchKernelGGL(k_mesh_emit<1>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
     return hipGetLastError();
 }
 

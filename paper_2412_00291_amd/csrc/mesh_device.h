@@ -1,148 +1,88 @@
-// Marching cubes of one 8^3 block by one workgroup (end of Sec. IV-C.3): the block and
-// its +1 halo (9^3 voxels of distance, weight and fused label, ~6.6 KiB) are staged in
-// LDS from up to eight blocks; each thread evaluates two cubes; a workgroup prefix sum of
-// the per-cube triangle counts reserves one contiguous output range with one atomic.
+// Marching cubes of 8^3 blocks (end of Sec. IV-C.3), in two passes over the same
+// candidate blocks: a counting pass (triangles per workgroup) and, after a scan of those
+// counts, an emitting pass that writes each block's triangles at its offset.  No
+// triangle reservation takes a shared atomic.  A worker (a workgroup, or a wavefront)
+// stages a block and its +1 halo (9^3 voxels of distance, weight and fused label,
+// ~6.6 KiB) in LDS from up to eight blocks, classifies the 512 cubes from the generated
+// case table, and emits vertices on the sign-change edges.
 #pragma once
 #include "device.h"
 #include "mc_table.inc"
 
 namespace mc {
 
-__device__ __forceinline__ void mesh_block(const MapView &m, int slot, const MeshOut &out,
-                                           unsigned long long *tris, MeshLds &S)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float nu = m.nu;
-    const int4 bc = m.coords[slot];
-    if (threadIdx.x < 8) {
-        const int j = threadIdx.x;
-        S.nb[j] = j == 0 ? slot : hash_find(m, pack_key(bc.x + (j & 1), bc.y + ((j >> 1) & 1), bc.z + ((j >> 2) & 1)));
-    }
-    __syncthreads();
-    for (int h = threadIdx.x; h < kHaloVoxels; h += kThreads) {
-        const int hx = h % kHalo, hy = (h / kHalo) % kHalo, hz = h / (kHalo * kHalo);
-        const int j = (hx >> 3) | ((hy >> 3) << 1) | ((hz >> 3) << 2);
-        const int s = S.nb[j];
-        if (s >= 0) {
-            const size_t vi = (size_t)s * kBlockVoxels + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7);
-            S.dw[h] = m.dw[vi];
-            S.fused[h] = m.fused[vi];
-        } else {
-            S.dw[h] = make_float2(0.0f, 0.0f);  // absent block: unobserved
-            S.fused[h] = 255;
-        }
-    }
-    __syncthreads();
-
-    int mask[2], ntri[2];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const int cube = it * kThreads + threadIdx.x;
-        const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
-        bool valid = true;
-        int mk = 0;
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            const float2 v = S.dw[halo_index(cx + (n & 1), cy + ((n >> 1) & 1), cz + ((n >> 2) & 1))];
-            valid = valid && (v.y > 0.0f);
-            mk |= (v.x < 0.0f ? 1 : 0) << n;
-        }
-        mask[it] = mk;
-        ntri[it] = valid ? (int)MC_NTRI[mk] : 0;
-    }
-    // workgroup exclusive scan of the triangle counts
-    const int mine = ntri[0] + ntri[1];
-    int incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-    }
-    if (lane == 63) S.wsum[wave] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int w = 0; w < kThreads / 64; ++w) tot += S.wsum[w];
-        S.base = tot ? atomicAdd(tris, (unsigned long long)tot) : 0ull;
-    }
-    __syncthreads();
-    int woff = 0;
-    for (int w = 0; w < wave; ++w) woff += S.wsum[w];
-    long long t = (long long)S.base + woff + (incl - mine);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const int cube = it * kThreads + threadIdx.x;
-        const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
-        for (int q = 0; q < ntri[it]; ++q, ++t) {
-            if (t >= out.cap) continue;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int ed = MC_TRIS[mask[it]][3 * q + k];
-                const int ax = ed >> 2;
-                const int3 o = edge_base(ed);
-                const int ax_ = cx + o.x, ay_ = cy + o.y, az_ = cz + o.z;
-                const int ha = halo_index(ax_, ay_, az_);
-                const int hb = halo_index(ax_ + (ax == 0), ay_ + (ax == 1), az_ + (ax == 2));
-                const float Da = S.dw[ha].x, Db = S.dw[hb].x;
-                const float tt = Da / (Da - Db);
-                const int vx = 8 * bc.x + ax_, vy = 8 * bc.y + ay_, vz = 8 * bc.z + az_;
-                float P[3] = {(float)vx * nu, (float)vy * nu, (float)vz * nu};
-                P[ax] = P[ax] + tt * nu;
-                float *dst = out.pos + (size_t)t * 9 + 3 * k;
-                dst[0] = P[0];
-                dst[1] = P[1];
-                dst[2] = P[2];
-                out.lab[(size_t)t * 3 + k] = fabsf(Da) <= fabsf(Db) ? S.fused[ha] : S.fused[hb];
-                if (out.ekey) {
-                    const long long off = 1LL << 19;
-                    out.ekey[(size_t)t * 3 + k] = ((vx + off) << 42) | ((vy + off) << 22) | ((vz + off) << 2) | ax;
-                }
-            }
-        }
-    }
-    __syncthreads();  // LDS reuse by the next block
-}
-
-// Close an extraction (one thread, after every worker has finished): clear the dirty set
-// when a DIRTY extraction fit in the output.
-__device__ __forceinline__ void close_extraction(const MapView &m, int mode, unsigned long long *tris, long long cap)
-{
-    const unsigned long long total = atomicAdd(tris, 0ull);
-    if (mode == 0 && (long long)total <= cap) {
-        m.ctr->n_dirty = 0;
-        m.ctr->dirty_epoch += 1;
-    }
-}
-
-}  // namespace mc
-
-namespace mc {
-
-// The same marching cubes of one block by one wavefront (8 cubes per lane), with the
-// halo in the wavefront's own LDS region: four blocks in flight per workgroup.
-struct MeshLdsWave {
+struct MeshHalo {
     float2 dw[kHaloVoxels];
     uint8_t fused[kHaloVoxels];
-    int nb[8];
 };
+
+// Candidates are meshed in batches of kMeshBatch blocks; a batch's block coordinates and
+// neighbour slots are looked up by the whole workgroup at once (eight lanes per block)
+// before any block of the batch is staged.
+constexpr int kMeshBatch = kThreads / 8;
+
+// LDS of a meshing workgroup: the case tables (read per cube and per vertex, so they
+// are copied from global memory once per workgroup), one halo per worker, the
+// iteration's candidate list and per-wave counts.
+constexpr int kTriRow = 3 * MC_MAX_TRIS;
+template <int kSched>
+struct MeshSmem {
+    uint8_t ntri[256];
+    int8_t tris[256 * kTriRow];
+    MeshHalo h[kSched == 0 ? 1 : kThreads / 64];
+    uint8_t ccase[kSched == 0 ? 1 : kThreads / 64][kBlockVoxels];  // case of every cube (emitting pass)
+    int4 rbc[kThreads / 64];                                        // block of each worker in a round
+    int4 bcs[kMeshBatch];
+    int nbs[kMeshBatch][8];
+    int mis[kMeshBatch];  // map of each batch entry (batched steps)
+    int list[kThreads];
+    int wcnt[kThreads / 64];
+    long long rcnt[kThreads / 64];
+};
+
+// Copy the case tables into the workgroup's LDS (every thread; a barrier follows).
+template <class Smem>
+__device__ __forceinline__ void mesh_tables(Smem &S)
+{
+    for (int i = threadIdx.x; i < 256; i += kThreads) S.ntri[i] = MC_NTRI[i];
+    for (int i = threadIdx.x; i < 256 * kTriRow; i += kThreads) S.tris[i] = MC_TRIS[i / kTriRow][i % kTriRow];
+    __syncthreads();
+}
 
 __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-__device__ __forceinline__ void mesh_block_wave(const MapView &m, int slot, const MeshOut &out,
-                                                unsigned long long *tris, MeshLdsWave &S)
+template <int kSched>
+__device__ __forceinline__ void worker_sync()
 {
-    const int lane = threadIdx.x & 63;
-    const float nu = m.nu;
-    const int4 bc = m.coords[slot];
-    if (lane < 8) {
-        const int j = lane;
-        S.nb[j] = j == 0 ? slot : hash_find(m, pack_key(bc.x + (j & 1), bc.y + ((j >> 1) & 1), bc.z + ((j >> 2) & 1)));
+    if (kSched == 0) __syncthreads();
+    else wave_lds_sync();
+}
+
+// Coordinates and neighbour slots (b + e, e in {0,1}^3; -1 when absent) of list entries
+// j0 .. j0 + nb - 1, nb <= kMeshBatch; every thread calls it.
+template <class Smem>
+__device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int j0, int nb)
+{
+    const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
+    if (jb < nb) {
+        const int slot = S.list[j0 + jb];
+        const int4 bc = m.coords[slot];
+        if (e == 0) S.bcs[jb] = bc;
+        S.nbs[jb][e] = e == 0 ? slot : hash_find(m, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
     }
-    wave_lds_sync();
-    for (int h = lane; h < kHaloVoxels; h += 64) {
+    __syncthreads();
+}
+
+// Stage the halo of the block whose neighbour slots are nb[8]; rank is the lane's index
+// among the worker's kWidth.
+template <int kSched>
+__device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, MeshHalo &S, int rank)
+{
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    for (int h = rank; h < kHaloVoxels; h += kWidth) {
         const int hx = h % kHalo, hy = (h / kHalo) % kHalo, hz = h / (kHalo * kHalo);
         const int j = (hx >> 3) | ((hy >> 3) << 1) | ((hz >> 3) << 2);
-        const int s = S.nb[j];
+        const int s = nb[j];
         if (s >= 0) {
             const size_t vi = (size_t)s * kBlockVoxels + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7);
             S.dw[h] = m.dw[vi];
@@ -152,71 +92,385 @@ __device__ __forceinline__ void mesh_block_wave(const MapView &m, int slot, cons
             S.fused[h] = 255;
         }
     }
-    wave_lds_sync();
-    unsigned masks = 0;  // triangle counts of the lane's 8 cubes, 4 bits each
+    worker_sync<kSched>();
+}
+
+// Cases of the lane's cubes (cube it * kWidth + rank): returns the lane's triangles,
+// packs each cube's triangle count into 4 bits of *counts, and stores each cube's case
+// in ccase[cube] when ccase is given.  A cube counts only when all eight corners are
+// observed (W > 0).
+template <int kSched>
+__device__ __forceinline__ int mesh_classify(const MeshHalo &S, const uint8_t *ntri, int rank, uint8_t *ccase,
+                                             unsigned *counts)
+{
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    constexpr int kCubes = kBlockVoxels / kWidth;
     int mine = 0;
-    int mk8[8];
+    unsigned packed = 0;
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
-        const int cube = it * 64 + lane;
+    for (int it = 0; it < kCubes; ++it) {
+        const int cube = it * kWidth + rank;
         const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
         bool valid = true;
-        int mk = 0;
+        int k = 0;
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
             const float2 v = S.dw[halo_index(cx + (n & 1), cy + ((n >> 1) & 1), cz + ((n >> 2) & 1))];
             valid = valid && (v.y > 0.0f);
-            mk |= (v.x < 0.0f ? 1 : 0) << n;
+            k |= (v.x < 0.0f ? 1 : 0) << n;
         }
-        const int nt = valid ? (int)MC_NTRI[mk] : 0;
-        mk8[it] = mk;
-        masks |= (unsigned)nt << (4 * it);
+        const int nt = valid ? (int)ntri[k] : 0;
+        if (ccase) ccase[cube] = (uint8_t)k;
+        packed |= (unsigned)nt << (4 * it);
         mine += nt;
     }
-    int incl = mine;
+    *counts = packed;
+    return mine;
+}
+
+// Triangles are emitted a window of kStageTris at a time: every lane records a 2-byte
+// descriptor (worker, cube, triangle of the cube) per triangle of its cubes in the
+// window, then each thread builds whole triangles (one per thread, consecutive threads
+// consecutive triangles) into an LDS stage, which the workgroup copies out with
+// consecutive-address stores.
+constexpr int kStageTris = 256;
+struct MeshStage {
+    float pos[kStageTris * 9];
+    uint8_t lab[kStageTris * 3];
+    uint16_t desc[kStageTris];  // worker << 12 | cube << 3 | triangle
+};
+
+// Descriptors of the lane's triangles whose index within the round lies in
+// [w0, w0 + kStageTris); lo is the lane's first index within the round.
+template <int kSched>
+__device__ __forceinline__ void mesh_desc(int worker, int rank, unsigned counts, int lo, int mine, int w0,
+                                          MeshStage &st)
+{
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    constexpr int kCubes = kBlockVoxels / kWidth;
+    if (mine == 0 || lo >= w0 + kStageTris || lo + mine <= w0) return;
+    int r = lo;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
+    for (int it = 0; it < kCubes; ++it) {
+        const int nt = (counts >> (4 * it)) & 15;
+        const int cube = it * kWidth + rank;
+        for (int q = 0; q < nt; ++q, ++r)
+            if (r >= w0 && r < w0 + kStageTris) st.desc[r - w0] = (uint16_t)((worker << 12) | (cube << 3) | q);
     }
-    const int tot = __shfl(incl, 63, 64);
-    unsigned long long base = 0;
-    if (lane == 0 && tot) base = atomicAdd(tris, (unsigned long long)tot);
-    base = __shfl(base, 0, 64);
-    long long t = (long long)base + (incl - mine);
+}
+
+// Build staged triangle i of the window from its descriptor; g is its output index.
+// Edge keys, when asked for, go straight to global memory (indices at or past out.cap
+// are dropped: the extraction then reports the size it needs).
+template <class Smem>
+__device__ __forceinline__ void mesh_tri(const MapView &m, const Smem &S, MeshStage &st, int i, long long g,
+                                         const MeshOut &out)
+{
+    const int d = st.desc[i];
+    const int wk = d >> 12, cube = (d >> 3) & 511, q = d & 7;
+    const MeshHalo &H = S.h[wk];
+    const int4 bc = S.rbc[wk];
+    const int8_t *row = S.tris + (int)S.ccase[wk][cube] * kTriRow + 3 * q;
+    const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
+    const float nu = m.nu;
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
-        const int cube = it * 64 + lane;
-        const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
-        const int nt = (masks >> (4 * it)) & 15;
-        for (int q = 0; q < nt; ++q, ++t) {
-            if (t >= out.cap) continue;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int ed = MC_TRIS[mk8[it]][3 * q + k];
-                const int ax = ed >> 2;
-                const int3 o = edge_base(ed);
-                const int ax_ = cx + o.x, ay_ = cy + o.y, az_ = cz + o.z;
-                const int ha = halo_index(ax_, ay_, az_);
-                const int hb = halo_index(ax_ + (ax == 0), ay_ + (ax == 1), az_ + (ax == 2));
-                const float Da = S.dw[ha].x, Db = S.dw[hb].x;
-                const float tt = Da / (Da - Db);
-                const int vx = 8 * bc.x + ax_, vy = 8 * bc.y + ay_, vz = 8 * bc.z + az_;
-                float P[3] = {(float)vx * nu, (float)vy * nu, (float)vz * nu};
-                P[ax] = P[ax] + tt * nu;
-                float *dst = out.pos + (size_t)t * 9 + 3 * k;
-                dst[0] = P[0];
-                dst[1] = P[1];
-                dst[2] = P[2];
-                out.lab[(size_t)t * 3 + k] = fabsf(Da) <= fabsf(Db) ? S.fused[ha] : S.fused[hb];
-                if (out.ekey) {
-                    const long long off = 1LL << 19;
-                    out.ekey[(size_t)t * 3 + k] = ((vx + off) << 42) | ((vy + off) << 22) | ((vz + off) << 2) | ax;
-                }
-            }
+    for (int k = 0; k < 3; ++k) {
+        const int ed = row[k];
+        const int ax = ed >> 2;
+        const int3 o = edge_base(ed);
+        const int ax_ = cx + o.x, ay_ = cy + o.y, az_ = cz + o.z;
+        const int ha = halo_index(ax_, ay_, az_);
+        const int hb = halo_index(ax_ + (ax == 0), ay_ + (ax == 1), az_ + (ax == 2));
+        const float Da = H.dw[ha].x, Db = H.dw[hb].x;
+        const float tt = Da / (Da - Db);
+        const int vx = 8 * bc.x + ax_, vy = 8 * bc.y + ay_, vz = 8 * bc.z + az_;
+        float P[3] = {(float)vx * nu, (float)vy * nu, (float)vz * nu};
+        P[ax] = P[ax] + tt * nu;
+        st.pos[i * 9 + 3 * k] = P[0];
+        st.pos[i * 9 + 3 * k + 1] = P[1];
+        st.pos[i * 9 + 3 * k + 2] = P[2];
+        st.lab[i * 3 + k] = fabsf(Da) <= fabsf(Db) ? H.fused[ha] : H.fused[hb];
+        if (out.ekey && g < out.cap) {
+            const long long off = 1LL << 19;
+            out.ekey[g * 3 + k] = ((vx + off) << 42) | ((vy + off) << 22) | ((vz + off) << 2) | ax;
         }
     }
-    wave_lds_sync();  // the halo is rewritten by the wave's next block
+}
+
+// Copy n staged triangles to output index g0 on (whole workgroup).
+__device__ __forceinline__ void mesh_flush(const MeshStage &st, int n, long long g0, const MeshOut &out)
+{
+    long long nc = out.cap - g0;
+    if (nc > n) nc = n;
+    if (nc <= 0) return;
+    float *pos = out.pos + g0 * 9;
+    for (int i = threadIdx.x; i < (int)nc * 9; i += kThreads) pos[i] = st.pos[i];
+    uint8_t *lab = out.lab + g0 * 3;
+    for (int i = threadIdx.x; i < (int)nc * 3; i += kThreads) lab[i] = st.lab[i];
+}
+
+// One round's output (its blocks' triangles are contiguous from output index r0): the
+// lane's triangles are [lo, lo + mine) within the round of rtot; every thread of the
+// workgroup calls it.
+template <int kSched, class Smem>
+__device__ __forceinline__ void mesh_round_out(const MapView &m, const Smem &S, MeshStage &st, bool has, int worker,
+                                               int rank, unsigned counts, int lo, int mine, int rtot, long long r0,
+                                               const MeshOut &out)
+{
+    for (int w0 = 0; w0 < rtot; w0 += kStageTris) {
+        const int nw = rtot - w0 < kStageTris ? rtot - w0 : kStageTris;
+        if (has) mesh_desc<kSched>(worker, rank, counts, lo, mine, w0, st);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nw; i += kThreads) mesh_tri(m, S, st, i, r0 + w0 + i, out);
+        __syncthreads();
+        mesh_flush(st, nw, r0 + w0, out);
+        __syncthreads();
+    }
+}
+
+// Inclusive wavefront scan.
+__device__ __forceinline__ int wave_scan_incl(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+
+// One iteration's candidate slots of this workgroup, compacted into S.list in slot order;
+// returns their number, or -1 past the end.  Candidates are the map's slots [0, nslots),
+// dealt out one at a time: thread t of workgroup w takes slot (it kThreads + t) G + w,
+// so a cluster of dirty slots spreads over all workgroups.  A slot is taken if `all` or
+// its dirty flag holds `epoch`, and (need_tris: the emitting pass) the counting pass
+// found triangles in it.
+template <int kSched>
+__device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint32_t epoch, int nslots, int it,
+                                               bool need_tris, MeshSmem<kSched> &S)
+{
+    if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= nslots) return -1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long slot = ((long long)it * kThreads + threadIdx.x) * gridDim.x + blockIdx.x;
+    bool take = slot < nslots && (all || m.dirty_flag[slot] == epoch);
+    if (need_tris && take) take = m.mesh_cnt[slot] != 0;
+    const unsigned long long bal = __ballot(take);
+    if (lane == 0) S.wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, n = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const int c = S.wcnt[w];
+        off += w < wave ? c : 0;
+        n += c;
+    }
+    if (take) S.list[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)slot;
+    __syncthreads();
+    return n;
+}
+
+// Counting pass of one workgroup: triangles and blocks over its candidates.
+template <int kSched>
+__device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32_t epoch, int nslots,
+                                              MeshSmem<kSched> &S, long long *tris, int *blocks)
+{
+    mesh_tables(S);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    long long my_tris = 0;
+    int my_blocks = 0;
+    unsigned counts;
+    for (int it = 0;; ++it) {
+        const int n = mesh_candidates<kSched>(m, all, epoch, nslots, it, false, S);
+        if (n < 0) break;
+        for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
+            const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
+            mesh_batch_lookup(m, S, j0, nb);
+            if (kSched == 0) {
+                for (int j = 0; j < nb; ++j) {
+                    mesh_stage<0>(m, S.nbs[j], S.h[0], threadIdx.x);
+                    const unsigned long long t =
+                        wave_sum_u64((unsigned long long)mesh_classify<0>(S.h[0], S.ntri, threadIdx.x, nullptr, &counts));
+                    if (lane == 0) S.rcnt[wave] = (long long)t;
+                    __syncthreads();
+                    if (threadIdx.x == 0) {
+                        long long tot = 0;
+                        for (int w = 0; w < kThreads / 64; ++w) tot += S.rcnt[w];
+                        m.mesh_cnt[S.nbs[j][0]] = (uint16_t)tot;
+                        my_tris += tot;
+                    }
+                    __syncthreads();  // the halo and counts are rewritten by the next block
+                }
+                my_blocks += nb;
+            } else {
+                for (int j = wave; j < nb; j += kThreads / 64) {
+                    mesh_stage<1>(m, S.nbs[j], S.h[wave], lane);
+                    const unsigned long long t =
+                        wave_sum_u64((unsigned long long)mesh_classify<1>(S.h[wave], S.ntri, lane, nullptr, &counts));
+                    wave_lds_sync();
+                    if (lane == 0) {
+                        m.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
+                        my_tris += (long long)t;
+                        my_blocks += 1;
+                    }
+                }
+                __syncthreads();  // the batch's lookups are rewritten by the next batch
+            }
+        }
+        __syncthreads();  // the list is rewritten by the next iteration
+    }
+    // workgroup totals (kept on thread 0 of a workgroup worker, lane 0 of a wave worker)
+    if (kSched == 0 && threadIdx.x != 0) my_blocks = 0;
+    unsigned long long t = wave_sum_u64((unsigned long long)my_tris);
+    unsigned long long b = wave_sum_u64((unsigned long long)my_blocks);
+    if (lane == 0) {
+        S.rcnt[wave] = (long long)t;
+        S.wcnt[wave] = (int)b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long tt = 0;
+        int bb = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            tt += S.rcnt[w];
+            bb += S.wcnt[w];
+        }
+        *tris = tt;
+        *blocks = bb;
+    }
+}
+
+// Emitting pass of one workgroup: the same candidates in the same order, triangles from
+// output index `base` on.  A round is one block (kSched 0) or one block per wave
+// (kSched 1); a round's output is contiguous, in wave order.
+template <int kSched>
+__device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_t epoch, int nslots, long long base,
+                                             const MeshOut &out, MeshSmem<kSched> &S, MeshStage &st)
+{
+    constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
+    mesh_tables(S);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rank = kSched == 0 ? (int)threadIdx.x : lane;
+    const int worker = kSched == 0 ? 0 : wave;
+    unsigned counts = 0;
+    long long carry = base;
+    for (int it = 0;; ++it) {
+        const int n = mesh_candidates<kSched>(m, all, epoch, nslots, it, true, S);
+        if (n < 0) break;
+        for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
+            const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
+            mesh_batch_lookup(m, S, j0, nb);
+            for (int r = 0; r < nb; r += kPerRound) {
+                const int j = r + worker;
+                const bool has = j < nb;
+                int mine = 0;
+                if (kSched == 0 || has) {
+                    mesh_stage<kSched>(m, S.nbs[j], S.h[worker], rank);
+                    if (rank == 0) S.rbc[worker] = S.bcs[j];
+                    mine = mesh_classify<kSched>(S.h[worker], S.ntri, rank, S.ccase[worker], &counts);
+                }
+                const int incl = wave_scan_incl(mine);
+                if (lane == 63) S.rcnt[wave] = incl;
+                __syncthreads();
+                int woff = 0, rtot = 0;
+#pragma unroll
+                for (int w = 0; w < kThreads / 64; ++w) {
+                    const int c = (int)S.rcnt[w];
+                    woff += w < wave ? c : 0;
+                    rtot += c;
+                }
+                mesh_round_out<kSched>(m, S, st, has, worker, rank, counts, woff + incl - mine, mine, rtot, carry, out);
+                carry += rtot;
+                __syncthreads();  // the round's counts are rewritten by the next round
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of one map's counts per emitting workgroup (one workgroup): offsets,
+// and the extraction's bookkeeping.  Emitting workgroup w covers counting workgroups
+// w + j G, j < k; entry w of the arrays is at index w * stride.  A DIRTY extraction whose
+// output fits clears the dirty set by advancing the epoch; the emitting pass meshes the
+// epoch recorded here.
+__device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const long long *wg_tris,
+                                              const int32_t *wg_blocks, long long *wg_off, int G, int k, int stride,
+                                              long long cap, unsigned long long *tris_out)
+{
+    __shared__ long long s_part[kThreads / 64];
+    __shared__ long long s_blk[kThreads / 64];
+    constexpr int kPer = kMaxMeshGrid / kThreads;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = (G + kThreads - 1) / kThreads;
+    const int w0 = threadIdx.x * per;
+    long long v[kPer];
+    long long sum = 0, blk = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        v[i] = 0;
+        if (i < per && w0 + i < G) {
+            for (int j = 0; j < k; ++j) {
+                const size_t idx = (size_t)(w0 + i + j * G) * stride;
+                v[i] += wg_tris[idx];
+                blk += wg_blocks[idx];
+            }
+        }
+        sum += v[i];
+    }
+    long long incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    const unsigned long long bw = wave_sum_u64((unsigned long long)blk);
+    if (lane == 63) s_part[wave] = incl;
+    if (lane == 0) s_blk[wave] = (long long)bw;
+    __syncthreads();
+    long long before = 0, total = 0, blocks = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        before += w < wave ? s_part[w] : 0;
+        total += s_part[w];
+        blocks += s_blk[w];
+    }
+    long long run = before + incl - sum;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        if (i < per && w0 + i < G) wg_off[(size_t)(w0 + i) * stride] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) {
+        Counters *c = m.ctr;
+        const uint32_t epoch = c->dirty_epoch;
+        c->mesh_epoch = epoch;
+        c->mesh_tris = (unsigned long long)total;
+        c->mesh_blocks = (unsigned long long)blocks;
+        if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
+        if (tris_out) *tris_out = (unsigned long long)total;
+    }
+}
+
+// Workgroups of the counting and emitting passes: each as many as the device holds at
+// once, the counting grid rounded down to a multiple of the emitting grid (emitting
+// workgroup w takes the slots of counting workgroups w + j G_emit), so every
+// workgroup's latency chain runs concurrently.
+template <class CountK, class EmitK>
+inline MeshGrid resident_grids(CountK count_k, EmitK emit_k)
+{
+    int dev = 0, cus = 0, a = 0, b = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, count_k, kThreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, emit_k, kThreads, 0) != hipSuccess || cus < 1 || a < 1 ||
+        b < 1)
+        return MeshGrid{1024, 1024};
+    long long ge = (long long)cus * b, gc = (long long)cus * a;
+    if (ge > kMaxMeshGrid) ge = kMaxMeshGrid;
+    if (gc > kMaxMeshGrid) gc = kMaxMeshGrid;
+    if (gc < ge) gc = ge;
+    gc -= gc % ge;
+    return MeshGrid{(int)ge, (int)gc};
 }
 
 }  // namespace mc

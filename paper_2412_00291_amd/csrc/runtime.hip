@@ -26,8 +26,7 @@ struct map_s {
     Counters *h_ctr = nullptr;  // pinned mirror for read-back
     hipStream_t last_stream = nullptr;
     bool has_scan = false;
-    int mesh_parity = 0;
-    int64_t last_tris = 0;
+    MeshScan scan{};        // extraction scratch, kMaxMeshGrid workgroups
     uint32_t frame_id = 0;  // integration calls so far (tags hash insertions)
     int sched[3] = {0, 0, 0};  // TSDF, labels, meshing: 0 workgroup / 1 wavefront per block
     std::string err;
@@ -87,9 +86,10 @@ static void free_all(map_t *m)
     for (hipEvent_t e : m->prof_free) (void)hipEventDestroy(e);
     m->prof_pending.clear();
     m->prof_free.clear();
-    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.hframe, m->v.dirty_flag,
-                    m->v.dirty_list, m->v.ctr, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
-                    m->f.tk_fslot, m->f.band, m->lut_buf, m->partial};
+    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.hframe,
+                    m->v.dirty_flag, m->v.mesh_cnt, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
+                    m->f.tk_fslot, m->f.band, m->lut_buf, m->partial, m->scan.wg_tris, m->scan.wg_blocks,
+                    m->scan.wg_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (m->h_ctr) (void)hipHostFree(m->h_ctr);
@@ -231,13 +231,18 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&v.hvals, hcap * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&v.hframe, hcap * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.dirty_flag, nb * sizeof(uint32_t)));
-    CREATE_TRY(hipMalloc(&v.dirty_list, nb * sizeof(int32_t)));
+    CREATE_TRY(hipMalloc(&v.mesh_cnt, nb * sizeof(uint16_t)));
     CREATE_TRY(hipMalloc(&v.ctr, sizeof(Counters)));
+    CREATE_TRY(hipMalloc(&v.sync, sizeof(SyncState)));
+    CREATE_TRY(hipMalloc(&m->scan.wg_tris, kMaxMeshGrid * sizeof(long long)));
+    CREATE_TRY(hipMalloc(&m->scan.wg_blocks, kMaxMeshGrid * sizeof(int32_t)));
+    CREATE_TRY(hipMalloc(&m->scan.wg_off, kMaxMeshGrid * sizeof(long long)));
     CREATE_TRY(hipHostMalloc((void **)&m->h_ctr, sizeof(Counters), hipHostMallocDefault));
     CREATE_TRY(hipMemsetAsync(v.dw, 0, nb * kBlockVoxels * sizeof(float2), s));
     CREATE_TRY(hipMemsetAsync(v.counts, 0, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t), s));
     CREATE_TRY(hipMemsetAsync(v.coords, 0, nb * sizeof(int4), s));
     CREATE_TRY(hipMemsetAsync(v.dirty_flag, 0, nb * sizeof(uint32_t), s));
+    CREATE_TRY(hipMemsetAsync(v.sync, 0, sizeof(SyncState), s));
     CREATE_TRY(hipMemsetAsync(v.hframe, 0xFF, hcap * sizeof(uint32_t), s));  // no insertion yet
     CREATE_TRY(launch_init_pool(v, s));
     CREATE_TRY(launch_fill_u64(v.hkeys, hcap, kEmpty, s));
@@ -455,17 +460,13 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
-    const int parity = m->mesh_parity;
-    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
-        return launch_mesh(m->v, mode, parity, out, m->sched[2], grid_for(m->p.max_blocks, 1, 2048), s);
-    }));
+    const MeshGrid grid = mesh_grid(m->sched[2]);
+    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] { return launch_mesh(m->v, mode, out, m->scan, m->sched[2], grid, s); }));
     HIP_TRY(m, hipMemcpyAsync(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(m, hipStreamSynchronize(s));
     m->last_stream = s;
-    m->mesh_parity = 1 - parity;
-    const int64_t n = (int64_t)m->h_ctr->tris[parity];
+    const int64_t n = (int64_t)m->h_ctr->mesh_tris;
     *n_tris = n;
-    m->last_tris = n;
     if (n > cap_tris)
         return fail(m, MAP_ERR_BUFFER_TOO_SMALL, "extract_mesh: %lld triangles, capacity %lld", (long long)n,
                     (long long)cap_tris);
@@ -558,9 +559,13 @@ extern "C" int map_stats(map_t *m, map_frame_stats *out)
     out->touched = c.last_touched;
     out->new_blocks = c.last_new;
     out->updates = (int64_t)c.last_updates;
-    out->votes = (int64_t)c.votes;
+    Spread votes;
+    HIP_TRY(m, hipMemcpy(&votes, &m->v.sync->votes, sizeof(Spread), hipMemcpyDeviceToHost));
+    unsigned long long nv = 0;
+    for (int l = 0; l < kLeaves; ++l) nv += votes.v[l * kLeafPad];
+    out->votes = (int64_t)nv;
     out->mesh_blocks = (int64_t)c.mesh_blocks;
-    out->triangles = m->last_tris;
+    out->triangles = (int64_t)c.mesh_tris;
     out->allocated = c.pool_used;
     out->frames = c.frames;
     return take_status(m);
@@ -663,6 +668,8 @@ struct map_batch_s {
     int device = 0;
     BatchMap *d_desc = nullptr, *h_desc = nullptr;
     BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
+    BatchSync *d_sync = nullptr;
+    MeshScan scan{};  // [kMaxMeshGrid][kMaxBatchMaps]
     int schedule = 0, grid = 2048;
     bool use_graph = true;
     // one executable graph per step shape (map count, tile count, schedule, grid, stream)
@@ -676,6 +683,9 @@ static void batch_free(map_batch_t *b)
     b->graphs.clear();
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_ctl) (void)hipFree(b->d_ctl);
+    void *ptrs[] = {b->d_sync, b->scan.wg_tris, b->scan.wg_blocks, b->scan.wg_off};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
 }
@@ -698,11 +708,16 @@ extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out
     bool ok = hipSetDevice(b->device) == hipSuccess &&
               hipMalloc(&b->d_desc, kMaxBatchMaps * sizeof(BatchMap)) == hipSuccess &&
               hipMalloc(&b->d_ctl, sizeof(BatchCtl)) == hipSuccess &&
+              hipMalloc(&b->d_sync, sizeof(BatchSync)) == hipSuccess &&
+              hipMalloc(&b->scan.wg_tris, (size_t)kMaxMeshGrid * kMaxBatchMaps * sizeof(long long)) == hipSuccess &&
+              hipMalloc(&b->scan.wg_blocks, (size_t)kMaxMeshGrid * kMaxBatchMaps * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&b->scan.wg_off, (size_t)kMaxMeshGrid * kMaxBatchMaps * sizeof(long long)) == hipSuccess &&
               hipHostMalloc((void **)&b->h_desc, kMaxBatchMaps * sizeof(BatchMap), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) == hipSuccess;
     if (ok) {
         std::memset(b->h_ctl, 0, sizeof(BatchCtl));
-        ok = hipMemcpy(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice) == hipSuccess;
+        ok = hipMemcpy(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemset(b->d_sync, 0, sizeof(BatchSync)) == hipSuccess;
     }
     if (!ok) {
         batch_free(b);
@@ -715,7 +730,7 @@ extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out
 
 extern "C" int map_batch_configure(map_batch_t *b, int32_t schedule, int32_t grid, int32_t use_graph)
 {
-    if (!b || (schedule != 0 && schedule != 1) || grid < 64 || grid > 65536) return MAP_ERR_INVALID_ARG;
+    if (!b || (schedule != 0 && schedule != 1) || grid < 64 || grid > kMaxMeshGrid) return MAP_ERR_INVALID_ARG;
     b->schedule = schedule;
     b->grid = grid;
     b->use_graph = use_graph != 0;
@@ -787,7 +802,6 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         d.out = MeshOut{it.pos_dev, it.lab_dev, (long long *)it.edge_keys_dev, (long long)it.cap_tris};
         d.tile0 = tiles;
         d.tiles = (it.lidar->rows * it.lidar->cols + 255) / 256;
-        d.parity = m->mesh_parity;
         d.frame_id = m->frame_id++;
         tiles += d.tiles;
     }
@@ -805,7 +819,7 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
             hipGraphExec_t ge = nullptr;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return fail_b(e, "graph capture");
-            hipError_t le = launch_batch(b->d_desc, b->d_ctl, n, tiles, b->schedule, b->grid, s);
+            hipError_t le = launch_batch(b->d_desc, b->d_ctl, b->d_sync, b->scan, n, tiles, b->schedule, b->grid, s);
             e = hipStreamEndCapture(s, &g);
             if (le != hipSuccess) return fail_b(le, "batched launch");
             if (e != hipSuccess) return fail_b(e, "graph capture end");
@@ -817,10 +831,10 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         e = hipGraphLaunch(itg->second, s);
         if (e != hipSuccess) return fail_b(e, "graph launch");
     } else {
-        e = launch_batch(b->d_desc, b->d_ctl, n, tiles, b->schedule, b->grid, s);
+        e = launch_batch(b->d_desc, b->d_ctl, b->d_sync, b->scan, n, tiles, b->schedule, b->grid, s);
         if (e != hipSuccess) return fail_b(e, "batched launch");
     }
-    e = hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(b->h_ctl->tris, b->d_ctl->tris, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return fail_b(e, "result read-back");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_b(e, "step");
@@ -829,8 +843,6 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         map_t *m = b->maps[items[i].map_index];
         const int64_t t = (int64_t)b->h_ctl->tris[i];
         n_tris[i] = t;
-        m->last_tris = t;
-        m->mesh_parity = 1 - m->mesh_parity;
         m->has_scan = true;
         m->last_stream = s;
         if (t > items[i].cap_tris) {

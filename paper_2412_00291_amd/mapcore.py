@@ -105,9 +105,15 @@ class LidarModel:
     r_max: float
 
     def _c(self):
+        key = (self.rows, self.cols, self.r_max, id(self.elev_rad))
+        cached = self.__dict__.get("_cstruct")
+        if cached is not None and cached[0] == key:
+            return cached[1]
         e = np.ascontiguousarray(self.elev_rad, dtype=np.float32)
         s = _Lidar(self.rows, self.cols, e.ctypes.data, self.r_max)
         s._keep = e
+        if e is self.elev_rad:  # reusable: the struct points at the model's own array
+            self.__dict__["_cstruct"] = (key, s)
         return s
 
 
