@@ -15,6 +15,7 @@ constexpr int kLdsKeys = 2048;                    // per-workgroup de-duplicatio
 constexpr int kKeysPerThread = kLdsKeys / kThreads;
 constexpr int kHalo = 9;
 constexpr int kHaloVoxels = kHalo * kHalo * kHalo;
+constexpr size_t kMaxLdsLut = 40 * 1024;  // boundary tables staged in LDS up to this size
 
 // ---------------------------------------------------------------------------------
 // reductions
@@ -71,13 +72,32 @@ __device__ __forceinline__ bool col_holds(const LidarLUT &L, int c, float px, fl
     return cross64(b1.x, b1.y, px, py) > 0.0 && cross64(b0.x, b0.y, px, py) <= 0.0;
 }
 
+// Approximate atan2(y, x) for initial guesses only (the exact predicates decide): an odd
+// polynomial in min/max(|x|, |y|) fitted (least squares, Lawson-weighted toward minimax)
+// to atan on [0, 1], maximum error 1.2e-5 rad, far below half a pixel of any scan.
+// Needs (x, y) != (0, 0).
+__device__ __forceinline__ float atan2_guess(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+    const float s = t * t;
+    float p = fmaf(s, 0.020848948f, -0.0851640022f);
+    p = fmaf(p, s, 0.180164277f);
+    p = fmaf(p, s, -0.330305951f);
+    p = fmaf(p, s, 0.9998664f);
+    float r = p * t;
+    if (ay > ax) r = 1.57079633f - r;
+    if (x < 0.0f) r = 3.14159265f - r;
+    return y < 0.0f ? -r : r;
+}
+
 // nearest pixel of a sensor-frame point, or false
 __device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float py, float pz, int &row,
                                               int &col)
 {
     if (px == 0.0f && py == 0.0f) return false;
     const float kPi = 3.14159265358979f;
-    float a = (kPi - atan2f(py, px)) * L.cols_over_2pi;
+    const float a = (kPi - atan2_guess(py, px)) * L.cols_over_2pi;
     int g = (int)floorf(a + 0.5f);
     g %= L.cols;
     if (g < 0) g += L.cols;
@@ -93,28 +113,32 @@ __device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float
             if (c < 0) return false;
         }
     }
-    const float rho = sqrtf(px * px + py * py);
-    // inside the vertical field of view: on or below boundary 0, strictly above boundary R
-    const float2 top = L.br[0], bot = L.br[L.rows];
-    if (cross64(top.x, top.y, rho, pz) > 0.0) return false;
-    if (cross64(bot.x, bot.y, rho, pz) <= 0.0) return false;
     // The row is the largest k in [0, rows-1] with the point on or below boundary k (the
-    // boundaries descend with k).  Start from the elevation's guess and walk: up while the
-    // point is above boundary k (boundary 0 stops it), then down while it is on or below
-    // boundary k+1.  Only the exact predicates decide, so the guess affects speed only.
-    int k = (int)floorf((L.el_top - atan2f(pz, rho)) * L.rows_over_fov);
-    k = k < 0 ? 0 : (k > L.rows - 1 ? L.rows - 1 : k);
-    for (;;) {
-        if (k == 0) break;
-        const float2 b = L.br[k];
-        if (cross64(b.x, b.y, rho, pz) <= 0.0) break;
-        --k;
-    }
-    for (;;) {
-        if (k + 1 >= L.rows) break;
-        const float2 b = L.br[k + 1];
-        if (cross64(b.x, b.y, rho, pz) > 0.0) break;
-        ++k;
+    // boundaries descend with k); the point is inside the vertical field of view when it
+    // is on or below boundary 0 and strictly above boundary rows.  Start from the
+    // elevation's guess and walk with the exact predicates: down while the point is on or
+    // below boundary k+1 (reaching boundary rows: outside), or up until it is on or below
+    // boundary k (passing boundary 0: outside).  The walk's end implies the field-of-view
+    // test, so the common case takes two predicates.
+    const float rho = sqrtf(px * px + py * py);
+    const int R = L.rows;
+    int k = (int)floorf((L.el_top - atan2_guess(pz, rho)) * L.rows_over_fov);
+    k = k < 0 ? 0 : (k > R - 1 ? R - 1 : k);
+    float2 b = L.br[k];
+    if (cross64(b.x, b.y, rho, pz) <= 0.0) {
+        for (;;) {
+            b = L.br[k + 1];
+            if (cross64(b.x, b.y, rho, pz) > 0.0) break;
+            if (k + 1 == R) return false;
+            ++k;
+        }
+    } else {
+        for (;;) {
+            if (k == 0) return false;
+            --k;
+            b = L.br[k];
+            if (cross64(b.x, b.y, rho, pz) <= 0.0) break;
+        }
     }
     row = k;
     col = c;
@@ -455,55 +479,80 @@ __device__ __forceinline__ int neighbour_slot(const MapView &m, int j, int3 bc, 
     return hash_find_old(m, pack_key(bc.x - (j & 1), bc.y - ((j >> 1) & 1), bc.z - ((j >> 2) & 1)), frame_id);
 }
 
-// Projective TSDF update of voxel li of a block; returns true if it updated, and sets band.
-__device__ __forceinline__ bool tsdf_voxel(const MapView &m, const LidarLUT &L, const Pose &T,
-                                           const float *__restrict__ range, float2 *dwb, int3 bc, int li, bool &band)
+// Projective TSDF update (Eq. 5), split so that a lane's voxels overlap their memory
+// reads: project a voxel to its nearest pixel (-1 if none, with the sensor-frame
+// distance), then update from the pixel's return.
+
+// Nearest pixel (row * cols + col, or -1) of voxel li of the block at bc, and its distance.
+__device__ __forceinline__ int tsdf_project(const MapView &m, const LidarLUT &L, const Pose &T, int3 bc, int li,
+                                            float &dist)
 {
-    const float nu = m.nu, tau = m.tau, two_tau = m.tau + m.tau;
-    band = false;
+    const float nu = m.nu;
     const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
     const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
     const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
     const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
     const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
     const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
+    dist = 0.0f;
     int row, col;
-    if (px == 0.0f && py == 0.0f && pz == 0.0f) return false;
-    if (!nearest_pixel(L, px, py, pz, row, col)) return false;
-    const float r = range[row * L.cols + col];
+    if (px == 0.0f && py == 0.0f && pz == 0.0f) return -1;
+    if (!nearest_pixel(L, px, py, pz, row, col)) return -1;
+    dist = sqrtf((px * px + py * py) + pz * pz);
+    return row * L.cols + col;
+}
+
+// Update (D, W) in v from return r at distance dist; true if updated.  band: |psi| <= tau.
+__device__ __forceinline__ bool tsdf_update(const MapView &m, const LidarLUT &L, float r, float dist, float2 &v,
+                                            bool &band)
+{
+    const float tau = m.tau, two_tau = m.tau + m.tau;
+    band = false;
     if (!valid_return(r, L.r_max)) return false;
-    const float dist = sqrtf((px * px + py * py) + pz * pz);
     const float psi = r - dist;
     if (psi < -tau) return false;
     float w = (psi + tau) / two_tau;
     if (w > 1.0f) w = 1.0f;
     if (w == 0.0f) return false;
     const float gam = psi < tau ? psi : tau;
-    float2 v = dwb[li];
     const float num = v.y * v.x + w * gam;
     const float den = v.y + w;
     v.x = num / den;
     v.y = den;
-    dwb[li] = v;
     band = fabsf(psi) <= tau;
     return true;
 }
 
 // The TSDF update of one touched block's voxels by one worker of kWidth lanes (rank is
 // the lane's index in the worker); records the block's band bits.  Returns the updates.
+// The lane's (D, W) loads are issued first, then its projections (LDS tables), then all
+// of its range reads, so a block costs one memory round trip.
 template <int kWidth>
 __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const FrameView &f, const LidarLUT &L,
                                                          const Pose &T, const float *__restrict__ range, int e,
                                                          unsigned long long key, int slot, int rank)
 {
+    constexpr int kV = kBlockVoxels / kWidth;
     const int3 bc = unpack_key(key);
     float2 *dwb = m.dw + (size_t)slot * kBlockVoxels;
+    float2 v[kV];
+    int pix[kV];
+    float dist[kV], r[kV];
+#pragma unroll
+    for (int it = 0; it < kV; ++it) v[it] = dwb[it * kWidth + rank];
+#pragma unroll
+    for (int it = 0; it < kV; ++it) pix[it] = tsdf_project(m, L, T, bc, it * kWidth + rank, dist[it]);
+#pragma unroll
+    for (int it = 0; it < kV; ++it) r[it] = pix[it] >= 0 ? range[pix[it]] : 0.0f;
     unsigned long long upd = 0;
 #pragma unroll
-    for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
+    for (int it = 0; it < kV; ++it) {
         const int li = it * kWidth + rank;
-        bool band;
-        upd += tsdf_voxel(m, L, T, range, dwb, bc, li, band);
+        bool band = false;
+        if (pix[it] >= 0 && tsdf_update(m, L, r[it], dist[it], v[it], band)) {
+            dwb[li] = v[it];
+            upd++;
+        }
         const unsigned long long bits = __ballot(band);
         if ((threadIdx.x & 63) == 0) f.band[(size_t)e * 8 + (li >> 6)] = bits;
     }

@@ -98,7 +98,19 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
             if (rank < kChunk) s_slot[rank] = my_slot;
             __syncthreads();
         }
-        {
+        for (int j = 0; j < kChunk; ++j) {
+            const int item = base + j * stride;
+            if (item >= total) break;
+            const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
+            const int mi = __builtin_amdgcn_readfirstlane(find_map(s_pre, n, item));  // uniform per worker
+            if (!ctl->fs[mi].ok) continue;
+            const BatchMap &B = maps[mi];
+            const int e = item - s_pre[mi];
+            unsigned long long upd = tsdf_block<kWidth>(B.v, B.f, B.lut, B.T, B.range, e, B.f.tk_key[e], slot, rank);
+            upd = wave_sum_u64(upd);
+            if (lane == 0 && upd) atomicAdd(&s_upd[mi], upd);
+        }
+        {  // dirty marks last, as in the per-map kernel
             const int i = rank >> 3;
             const int im = base + i * stride;
             const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
@@ -112,18 +124,6 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
                     if (s >= 0) v.dirty_flag[s] = fs.epoch;
                 }
             }
-        }
-        for (int j = 0; j < kChunk; ++j) {
-            const int item = base + j * stride;
-            if (item >= total) break;
-            const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
-            const int mi = __builtin_amdgcn_readfirstlane(find_map(s_pre, n, item));  // uniform per worker
-            if (!ctl->fs[mi].ok) continue;
-            const BatchMap &B = maps[mi];
-            const int e = item - s_pre[mi];
-            unsigned long long upd = tsdf_block<kWidth>(B.v, B.f, B.lut, B.T, B.range, e, B.f.tk_key[e], slot, rank);
-            upd = wave_sum_u64(upd);
-            if (lane == 0 && upd) atomicAdd(&s_upd[mi], upd);
         }
         if (kSched == 0) __syncthreads();
     }
@@ -195,8 +195,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_labels(BatchMap *maps, Batch
 // One iteration's candidates of this workgroup over the step's concatenated pool slots
 // (map m's slots are items pre[m] .. pre[m+1]-1), compacted into S.list as item numbers;
 // dealt out as in the per-map passes.  Returns their number, or -1 past the end.
+template <class Smem>
 __device__ __forceinline__ int batch_candidates(const BatchMap *maps, const int *s_pre, const uint32_t *s_epoch,
-                                                int n, int it, bool need_tris, MeshSmem<0> &S)
+                                                int n, int it, bool need_tris, Smem &S)
 {
     const int total = s_pre[n];
     if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= total) return -1;
@@ -226,8 +227,8 @@ __device__ __forceinline__ int batch_candidates(const BatchMap *maps, const int 
 
 // Map, coordinates and neighbour slots of list entries j0 .. j0 + nb - 1 (as
 // mesh_batch_lookup, the map resolved per entry).
-__device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_pre, int n, MeshSmem<0> &S, int j0,
-                                             int nb)
+template <class Smem>
+__device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_pre, int n, Smem &S, int j0, int nb)
 {
     const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
     if (jb < nb) {
@@ -247,7 +248,7 @@ __device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_
 
 __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
 {
-    __shared__ MeshSmem<0> S;
+    __shared__ MeshSmem<0, HaloCode> S;
     __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ uint32_t s_epoch[kMaxBatchMaps];
     __shared__ long long s_tris[kMaxBatchMaps];
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
         s_blocks[m] = 0;
     }
     load_prefix(s_pre, ctl->pre_p, n);
-    mesh_tables(S);
+    mesh_tables(S, false);
     unsigned counts;
     for (int it = 0;; ++it) {
         const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, false, S);
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_scan(BatchMap *maps, Ba
 
 __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
 {
-    __shared__ MeshSmem<0> S;
+    __shared__ MeshSmem<0, HaloFull> S;
     __shared__ MeshStage st;
     __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ uint32_t s_epoch[kMaxBatchMaps];
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
         s_next[m] = scan.wg_off[(size_t)blockIdx.x * n + m];
     }
     load_prefix(s_pre, ctl->pre_p, n);
-    mesh_tables(S);
+    mesh_tables(S, true);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned counts;
     for (int it = 0;; ++it) {

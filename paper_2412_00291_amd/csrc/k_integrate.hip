@@ -73,19 +73,32 @@ hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lu
 // TSDF integration over the touched blocks (grid-stride); the last workgroup (by a
 // hierarchical ticket) closes the frame.  A worker is a workgroup (kSched 0, two voxels per thread) or a wavefront
 // (kSched 1, eight voxels per lane, four workers per workgroup).  A worker takes its
-// entries a chunk at a time: the chunk's commits run on one lane each and its neighbour
-// marks on eight lanes each, all at once, before the voxels of each entry in turn.
+// entries a chunk at a time: the chunk's commits run on one lane each, then the voxels of
+// each entry in turn, then the neighbour marks on eight lanes per entry, all at once.
 // ---------------------------------------------------------------------------------
 
-template <int kSched>
+// The nearest-pixel search reads the column and row boundary tables for every voxel; a
+// workgroup copies them (cols + rows + 1 pairs, 17 KiB for 2048 columns) into dynamic LDS
+// when the launch provides it (kLdsLut), so that the range image is the voxel's only
+// global read on the way to its update.
+template <int kSched, bool kLdsLut>
 __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, LidarLUT L, Pose T,
                                                   const float *__restrict__ range, uint32_t frame_id)
 {
     constexpr int kWidth = kSched == 0 ? kThreads : 64;
     constexpr int kChunk = kWidth / 8;  // entries per chunk: eight marking lanes each
+    extern __shared__ float2 s_lut[];
     __shared__ int s_slot[kThreads / 8];
     __shared__ int s_last;
     __shared__ unsigned long long s_sum[kThreads / 64];
+    if (kLdsLut) {
+        const int nc = L.cols, nr = L.rows + 1;
+        for (int i = threadIdx.x; i < nc; i += kThreads) s_lut[i] = L.bc[i];
+        for (int i = threadIdx.x; i < nr; i += kThreads) s_lut[nc + i] = L.br[i];
+        L.bc = s_lut;
+        L.br = s_lut + nc;
+        __syncthreads();
+    }
     const FrameState fs = frame_state(m, f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
@@ -101,18 +114,19 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
             __syncthreads();
         }
         if (fs.ok) {
+            for (int j = 0; j < kChunk; ++j) {
+                const int e = base + j * stride;
+                if (e >= fs.n_list) break;
+                const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
+                my_updates += tsdf_block<kWidth>(m, f, L, T, range, e, f.tk_key[e], slot, rank);
+            }
+            // dirty marks last: nothing above waits for their hash probes
             const int i = rank >> 3;  // lane r marks neighbour r % 8 of entry r / 8
             const int em = base + i * stride;
             const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
             if (em < fs.n_list) {
                 const int s = neighbour_slot(m, rank & 7, unpack_key(f.tk_key[em]), si, frame_id);
                 if (s >= 0) m.dirty_flag[s] = fs.epoch;
-            }
-            for (int j = 0; j < kChunk; ++j) {
-                const int e = base + j * stride;
-                if (e >= fs.n_list) break;
-                const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
-                my_updates += tsdf_block<kWidth>(m, f, L, T, range, e, f.tk_key[e], slot, rank);
             }
         }
         if (kSched == 0) __syncthreads();  // s_slot is rewritten by the next chunk
@@ -133,8 +147,18 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
 hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
                        const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s)
 {
-    if (schedule == 0) hipLaunchKernelGGL(k_tsdf<0>, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
-    else hipLaunchKernelGGL(k_tsdf<1>, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+    const size_t lds = ((size_t)lut.cols + lut.rows + 1) * sizeof(float2);
+    if (lds <= kMaxLdsLut) {
+        if (schedule == 0)
+            hipLaunchKernelGGL((k_tsdf<0, true>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
+        else
+            hipLaunchKernelGGL((k_tsdf<1, true>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
+    } else {
+        if (schedule == 0)
+            hipLaunchKernelGGL((k_tsdf<0, false>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+        else
+            hipLaunchKernelGGL((k_tsdf<1, false>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+    }
     return hipGetLastError();
 }
 

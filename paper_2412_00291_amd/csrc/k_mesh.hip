@@ -9,7 +9,7 @@ namespace mc {
 template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, MeshScan scan)
 {
-    __shared__ MeshSmem<kSched> S;
+    __shared__ MeshSmem<kSched, HaloCode> S;
     const Counters *c = m.ctr;
     long long tris;
     int blocks;
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kThreads) void k_mesh_scan(MapView m, int mode, Mes
 template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_mesh_emit(MapView m, int mode, MeshScan scan, MeshOut out)
 {
-    __shared__ MeshSmem<kSched> S;
+    __shared__ MeshSmem<kSched, HaloFull> S;
     __shared__ MeshStage st;
     const Counters *c = m.ctr;
     mesh_emit_wg<kSched>(m, mode != 0, c->mesh_epoch, c->pool_used, scan.wg_off[blockIdx.x], out, S, st);

@@ -11,8 +11,14 @@
 
 namespace mc {
 
-struct MeshHalo {
-    float2 dw[kHaloVoxels];
+// A staged halo: per voxel a code byte (bit 0: D < 0, bit 1: W > 0) for the cube cases;
+// the emitting pass also keeps D and the fused label for the vertices.
+struct HaloCode {
+    uint8_t code[kHaloVoxels];
+};
+struct HaloFull {
+    float d[kHaloVoxels];
+    uint8_t code[kHaloVoxels];
     uint8_t fused[kHaloVoxels];
 };
 
@@ -22,15 +28,16 @@ struct MeshHalo {
 constexpr int kMeshBatch = kThreads / 8;
 
 // LDS of a meshing workgroup: the case tables (read per cube and per vertex, so they
-// are copied from global memory once per workgroup), one halo per worker, the
-// iteration's candidate list and per-wave counts.
+// are copied from global memory once per workgroup; the counting pass needs only the
+// triangle counts), one halo per worker, the iteration's candidate list and per-wave
+// counts.
 constexpr int kTriRow = 3 * MC_MAX_TRIS;
-template <int kSched>
+template <int kSched, class Halo>
 struct MeshSmem {
     uint8_t ntri[256];
-    int8_t tris[256 * kTriRow];
-    MeshHalo h[kSched == 0 ? 1 : kThreads / 64];
-    uint8_t ccase[kSched == 0 ? 1 : kThreads / 64][kBlockVoxels];  // case of every cube (emitting pass)
+    int8_t tris[sizeof(Halo) == sizeof(HaloFull) ? 256 * kTriRow : 4];
+    Halo h[kSched == 0 ? 1 : kThreads / 64];
+    uint8_t ccase[kSched == 0 ? 1 : kThreads / 64][sizeof(Halo) == sizeof(HaloFull) ? kBlockVoxels : 4];  // emitting
     int4 rbc[kThreads / 64];                                        // block of each worker in a round
     int4 bcs[kMeshBatch];
     int nbs[kMeshBatch][8];
@@ -42,10 +49,11 @@ struct MeshSmem {
 
 // Copy the case tables into the workgroup's LDS (every thread; a barrier follows).
 template <class Smem>
-__device__ __forceinline__ void mesh_tables(Smem &S)
+__device__ __forceinline__ void mesh_tables(Smem &S, bool with_tris)
 {
     for (int i = threadIdx.x; i < 256; i += kThreads) S.ntri[i] = MC_NTRI[i];
-    for (int i = threadIdx.x; i < 256 * kTriRow; i += kThreads) S.tris[i] = MC_TRIS[i / kTriRow][i % kTriRow];
+    if (with_tris)
+        for (int i = threadIdx.x; i < 256 * kTriRow; i += kThreads) S.tris[i] = MC_TRIS[i / kTriRow][i % kTriRow];
     __syncthreads();
 }
 
@@ -73,22 +81,41 @@ __device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int
     __syncthreads();
 }
 
-// Stage the halo of the block whose neighbour slots are nb[8]; rank is the lane's index
-// among the worker's kWidth.
+__device__ __forceinline__ uint8_t voxel_code(float2 v)
+{
+    return (uint8_t)((v.x < 0.0f ? 1 : 0) | (v.y > 0.0f ? 2 : 0));
+}
+
+// Stage the halo of the block whose neighbour slots are nb[8] (absent blocks are
+// unobserved); rank is the lane's index among the worker's kWidth.
 template <int kSched>
-__device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, MeshHalo &S, int rank)
+__device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, HaloCode &S, int rank)
 {
     constexpr int kWidth = kSched == 0 ? kThreads : 64;
     for (int h = rank; h < kHaloVoxels; h += kWidth) {
         const int hx = h % kHalo, hy = (h / kHalo) % kHalo, hz = h / (kHalo * kHalo);
-        const int j = (hx >> 3) | ((hy >> 3) << 1) | ((hz >> 3) << 2);
-        const int s = nb[j];
+        const int s = nb[(hx >> 3) | ((hy >> 3) << 1) | ((hz >> 3) << 2)];
+        S.code[h] = s >= 0 ? voxel_code(m.dw[(size_t)s * kBlockVoxels + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7)]) : 0;
+    }
+    worker_sync<kSched>();
+}
+
+template <int kSched>
+__device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, HaloFull &S, int rank)
+{
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    for (int h = rank; h < kHaloVoxels; h += kWidth) {
+        const int hx = h % kHalo, hy = (h / kHalo) % kHalo, hz = h / (kHalo * kHalo);
+        const int s = nb[(hx >> 3) | ((hy >> 3) << 1) | ((hz >> 3) << 2)];
         if (s >= 0) {
             const size_t vi = (size_t)s * kBlockVoxels + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7);
-            S.dw[h] = m.dw[vi];
+            const float2 v = m.dw[vi];
+            S.d[h] = v.x;
+            S.code[h] = voxel_code(v);
             S.fused[h] = m.fused[vi];
         } else {
-            S.dw[h] = make_float2(0.0f, 0.0f);  // absent block: unobserved
+            S.d[h] = 0.0f;
+            S.code[h] = 0;
             S.fused[h] = 255;
         }
     }
@@ -99,8 +126,8 @@ __device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, Mesh
 // packs each cube's triangle count into 4 bits of *counts, and stores each cube's case
 // in ccase[cube] when ccase is given.  A cube counts only when all eight corners are
 // observed (W > 0).
-template <int kSched>
-__device__ __forceinline__ int mesh_classify(const MeshHalo &S, const uint8_t *ntri, int rank, uint8_t *ccase,
+template <int kSched, class Halo>
+__device__ __forceinline__ int mesh_classify(const Halo &S, const uint8_t *ntri, int rank, uint8_t *ccase,
                                              unsigned *counts)
 {
     constexpr int kWidth = kSched == 0 ? kThreads : 64;
@@ -111,13 +138,12 @@ __device__ __forceinline__ int mesh_classify(const MeshHalo &S, const uint8_t *n
     for (int it = 0; it < kCubes; ++it) {
         const int cube = it * kWidth + rank;
         const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
-        bool valid = true;
-        int k = 0;
+        int valid = 2, k = 0;
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
-            const float2 v = S.dw[halo_index(cx + (n & 1), cy + ((n >> 1) & 1), cz + ((n >> 2) & 1))];
-            valid = valid && (v.y > 0.0f);
-            k |= (v.x < 0.0f ? 1 : 0) << n;
+            const int c = S.code[halo_index(cx + (n & 1), cy + ((n >> 1) & 1), cz + ((n >> 2) & 1))];
+            valid &= c;
+            k |= (c & 1) << n;
         }
         const int nt = valid ? (int)ntri[k] : 0;
         if (ccase) ccase[cube] = (uint8_t)k;
@@ -168,7 +194,7 @@ __device__ __forceinline__ void mesh_tri(const MapView &m, const Smem &S, MeshSt
 {
     const int d = st.desc[i];
     const int wk = d >> 12, cube = (d >> 3) & 511, q = d & 7;
-    const MeshHalo &H = S.h[wk];
+    const HaloFull &H = S.h[wk];
     const int4 bc = S.rbc[wk];
     const int8_t *row = S.tris + (int)S.ccase[wk][cube] * kTriRow + 3 * q;
     const int cx = cube & 7, cy = (cube >> 3) & 7, cz = cube >> 6;
@@ -181,7 +207,7 @@ __device__ __forceinline__ void mesh_tri(const MapView &m, const Smem &S, MeshSt
         const int ax_ = cx + o.x, ay_ = cy + o.y, az_ = cz + o.z;
         const int ha = halo_index(ax_, ay_, az_);
         const int hb = halo_index(ax_ + (ax == 0), ay_ + (ax == 1), az_ + (ax == 2));
-        const float Da = H.dw[ha].x, Db = H.dw[hb].x;
+        const float Da = H.d[ha], Db = H.d[hb];
         const float tt = Da / (Da - Db);
         const int vx = 8 * bc.x + ax_, vy = 8 * bc.y + ay_, vz = 8 * bc.z + az_;
         float P[3] = {(float)vx * nu, (float)vy * nu, (float)vz * nu};
@@ -246,9 +272,9 @@ __device__ __forceinline__ int wave_scan_incl(int v)
 // so a cluster of dirty slots spreads over all workgroups.  A slot is taken if `all` or
 // its dirty flag holds `epoch`, and (need_tris: the emitting pass) the counting pass
 // found triangles in it.
-template <int kSched>
+template <class Smem>
 __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint32_t epoch, int nslots, int it,
-                                               bool need_tris, MeshSmem<kSched> &S)
+                                               bool need_tris, Smem &S)
 {
     if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= nslots) return -1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -273,15 +299,15 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
 // Counting pass of one workgroup: triangles and blocks over its candidates.
 template <int kSched>
 __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32_t epoch, int nslots,
-                                              MeshSmem<kSched> &S, long long *tris, int *blocks)
+                                              MeshSmem<kSched, HaloCode> &S, long long *tris, int *blocks)
 {
-    mesh_tables(S);
+    mesh_tables(S, false);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     long long my_tris = 0;
     int my_blocks = 0;
     unsigned counts;
     for (int it = 0;; ++it) {
-        const int n = mesh_candidates<kSched>(m, all, epoch, nslots, it, false, S);
+        const int n = mesh_candidates(m, all, epoch, nslots, it, false, S);
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
@@ -345,17 +371,17 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
 // (kSched 1); a round's output is contiguous, in wave order.
 template <int kSched>
 __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_t epoch, int nslots, long long base,
-                                             const MeshOut &out, MeshSmem<kSched> &S, MeshStage &st)
+                                             const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st)
 {
     constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
-    mesh_tables(S);
+    mesh_tables(S, true);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int worker = kSched == 0 ? 0 : wave;
     unsigned counts = 0;
     long long carry = base;
     for (int it = 0;; ++it) {
-        const int n = mesh_candidates<kSched>(m, all, epoch, nslots, it, true, S);
+        const int n = mesh_candidates(m, all, epoch, nslots, it, true, S);
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
