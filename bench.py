@@ -77,6 +77,29 @@ def algorithmic_bytes(kernel, s, rows, cols, cams):
     return 0
 
 
+def measured_traffic(kernel, sched):
+    """HBM bytes per launch of a kernel group from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel sources (or the schedules) differ from the
+    ones the counters were taken on."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "street_64x2048_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    csrc = os.path.join(root, "paper_2412_00291_amd", "csrc")
+    names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".h"))) + ["gen_mc_table.py"]
+    h = hashlib.sha256()
+    for n in sorted(os.path.join("paper_2412_00291_amd/csrc", x) for x in names):
+        h.update(open(os.path.join(root, n), "rb").read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    if any(rec.get("schedules", {}).get(k) != v for k, v in sched.items()):
+        return None
+    return rec.get("bytes_per_launch", {}).get(kernel)
+
+
 def cpu_baseline(w, frames, budget_s):
     import oracle
     om = oracle.OracleMap(w.voxel, w.trunc, w.n_classes, w.max_blocks)
@@ -398,8 +421,11 @@ def main():
     launches = prof_dom[1]
     dom_avg_us = 1e3 * prof_dom[0] / launches
     achieved = (alg / launches) / (dom_avg_us * 1e-6)
+    traffic = measured_traffic(dominant, {"tsdf": sched[0], "labels": sched[1], "mesh": sched[2]})
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM,
+                "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
                 "alg_bytes_per_launch": alg / launches, "avg_us_timed_region": dom_avg_us}
     integ_ms = sum(kern[k]["total_ms"] for k in ("alloc", "tsdf", "labels") if k in kern)
     mesh_ms = kern.get("mesh", {"total_ms": float("nan")})["total_ms"]
