@@ -218,16 +218,24 @@ def bench_batched(torch):
     sched, grid, timings = autotune.tune(sig, build, run_step, n_steps=2)
     log(f"[bench] batched: autotuner chose schedule {sched}, grid {grid}")
 
-    # batched, all steps
+    # batched, all steps (items prepared beforehand, as a caller holding its frames would);
+    # HIP events on the step stream give the device time of each step beside the wall time
+    step_items = [items_for(k) for k in range(n_steps)]
     batch = build()
     batch.configure(sched, grid, True)
-    run_step(batch, 0)  # first step: scratch sizing and graph capture (untimed)
+    with torch.cuda.stream(stream):
+        batch.step(step_items[0])  # first step: scratch sizing and graph capture (untimed)
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
     t0 = time.perf_counter()
-    for k in range(1, n_steps):
-        run_step(batch, k)
+    with torch.cuda.stream(stream):
+        for k in range(1, n_steps):
+            ev[k][0].record(stream)
+            batch.step(step_items[k])
+            ev[k][1].record(stream)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    gpu_batch = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(1, n_steps))
     U = 0
     for m in batch.maps:
         U += m.stats()[1]["updates"]
@@ -245,22 +253,30 @@ def bench_batched(torch):
 
     seq_step(0)
     torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
     t0 = time.perf_counter()
     for k in range(1, n_steps):
+        ev[k][0].record(cur)
         seq_step(k)
+        ev[k][1].record(cur)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    gpu_seq = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(1, n_steps))
     frames_timed = sum(max(len(d[3]) - 1, 0) for d in data)
     for m in maps + batch.maps:
         m.close()
     batch.close()
     return {"workload": "16 street maps, voxel 0.05-0.4 m, 16/32/64 x 1024-2048, 4-8 frames, 1 camera",
             "steps_timed": n_steps - 1, "map_frames_timed": frames_timed,
-            "schedule": {"tsdf_labels": ["workgroup-per-block", "wavefront-per-block"][sched], "grid": grid},
+            "schedule": {"tsdf": ["workgroup-per-block", "wavefront-per-block"][sched & 1],
+                         "labels": ["workgroup-per-block", "wavefront-per-block"][sched >> 1],
+                         "meshing": "wavefront-per-block", "grid": grid},
             "autotune_ms": {f"{k[0]},{k[1]}": 1e3 * v for k, v in timings.items()},
             "ms_per_step_batched": 1e3 * t_batch / (n_steps - 1),
             "ms_per_step_sequential": 1e3 * t_seq / (n_steps - 1),
             "speedup_vs_sequential": t_seq / t_batch,
+            "stream_ms_per_step_batched": gpu_batch / (n_steps - 1),
+            "stream_ms_per_step_sequential": gpu_seq / (n_steps - 1),
             "last_frame_updates_sum": U}
 
 

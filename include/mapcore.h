@@ -178,9 +178,10 @@ typedef struct {
 } map_batch_item;
 
 int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out);
-/* schedule: 0 = one workgroup per touched block, 1 = one wavefront per touched block;
- * grid: workgroups of the persistent phases (64..4096); use_graph: capture each step
- * shape once in a hipGraph and replay it. */
+/* schedule: bit 0 for the TSDF phase, bit 1 for the label phase, each 0 = one workgroup
+ * per touched block, 1 = one wavefront per touched block (so 0..3); grid: workgroups of
+ * those phases (64..4096); use_graph: capture each step shape once in a hipGraph and
+ * replay it.  Returns MAP_ERR_INVALID_ARG for values out of range. */
 int map_batch_configure(map_batch_t *batch, int32_t schedule, int32_t grid, int32_t use_graph);
 int map_batch_step(map_batch_t *batch, const map_batch_item *items, int32_t n_items, int64_t *n_tris,
                    void *stream);

@@ -12,7 +12,9 @@ import json
 import os
 import time
 
-CANDIDATES = [(0, 1024), (0, 2048), (0, 4096), (1, 1024), (1, 2048), (1, 4096)]
+# (schedule, grid): schedule bit 0 = TSDF, bit 1 = labels, each 0 workgroup / 1 wavefront
+# per touched block
+CANDIDATES = [(s, g) for s in (0, 1, 2, 3) for g in (1024, 2048, 4096)]
 
 
 def cache_path():

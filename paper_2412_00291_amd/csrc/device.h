@@ -597,10 +597,12 @@ __device__ __forceinline__ void close_frame_wave(const MapView &m, const FrameSt
 // label fusion (Eq. 6 as vote counts): one band voxel, every camera of the set in order
 // ---------------------------------------------------------------------------------
 
+// Called only for band voxels of the last frame; a band voxel was updated by that frame,
+// so its weight is positive and the W > 0 condition of the label update holds without a
+// read of W.
 __device__ __forceinline__ int label_voxel(const MapView &m, const CameraSet &cs, int slot, int3 bc, int li)
 {
     const size_t vi = (size_t)slot * kBlockVoxels + li;
-    if (!(m.dw[vi].y > 0.0f)) return 0;
     const float nu = m.nu;
     const int L = m.n_classes;
     const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);

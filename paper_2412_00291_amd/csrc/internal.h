@@ -82,6 +82,13 @@ struct MeshScan {
     long long *wg_off;
 };
 
+// An extraction's totals, written by the scan kernel straight into host-mapped pinned
+// memory, so the host reads them after the stream wait without a copy launch.
+struct MeshReport {
+    unsigned long long tris;
+    unsigned long long blocks;
+};
+
 // Per-frame scratch: frame set (de-duplication of the frame's blocks) and touched list.
 struct FrameView {
     unsigned long long *fkeys;  // [fmask + 1]
@@ -202,7 +209,6 @@ struct BatchCtl {  // device
     int32_t pre_t[kMaxBatchMaps + 1];  // prefix sums over maps: touched entries
     int32_t pre_l[kMaxBatchMaps + 1];  // label entries
     int32_t pre_p[kMaxBatchMaps + 1];  // mesh candidates (pool slots)
-    unsigned long long tris[kMaxBatchMaps];  // triangle count per map (read back)
 };
 
 struct BatchSync {  // device, zero-initialised
@@ -210,8 +216,8 @@ struct BatchSync {  // device, zero-initialised
     Ticket tsdf;
 };
 
-hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan scan, int n_maps, int total_tiles,
-                        int schedule, int grid, hipStream_t s);
+hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan scan, MeshReport *reports,
+                        int n_maps, int total_tiles, int schedule, int grid, hipStream_t s);
 
 hipError_t launch_init_pool(const MapView &m, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
@@ -228,8 +234,8 @@ struct MeshGrid {
 };
 MeshGrid mesh_grid(int schedule);
 MeshGrid batch_mesh_grid();
-hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, int schedule,
-                       MeshGrid grid, hipStream_t s);
+hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, MeshReport *report,
+                       int schedule, MeshGrid grid, hipStream_t s);
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
                         uint8_t *valid, hipStream_t s);
 hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,

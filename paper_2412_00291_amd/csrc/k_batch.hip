@@ -7,9 +7,10 @@
 // last workgroup of the allocation and TSDF phases (hierarchical tickets) does the
 // per-map bookkeeping and lays out the next phase's prefix sums.
 //
-// Schedules for the TSDF and label phases: 0 = one workgroup per touched block (two
-// voxels per thread), 1 = one wavefront per touched block (eight voxels per lane, four
-// blocks in flight per workgroup).  The project's autotuner picks the schedule and grid.
+// Schedules for the TSDF and label phases (bit 0 and bit 1 of the schedule): 0 = one
+// workgroup per touched block (two voxels per thread), 1 = one wavefront per touched block
+// (eight voxels per lane, four blocks in flight per workgroup).  Meshing uses one wavefront
+// per block.  The project's autotuner picks the schedules and the grid.
 #include "mesh_device.h"
 
 namespace mc {
@@ -246,13 +247,15 @@ __device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_
     __syncthreads();
 }
 
+// One wavefront per block, four blocks in flight per workgroup (as the per-map passes'
+// wavefront schedule); per-map totals are summed in LDS.
 __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
 {
-    __shared__ MeshSmem<0, HaloCode> S;
+    __shared__ MeshSmem<1, HaloCode> S;
     __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ uint32_t s_epoch[kMaxBatchMaps];
-    __shared__ long long s_tris[kMaxBatchMaps];
-    __shared__ int s_blocks[kMaxBatchMaps];
+    __shared__ unsigned long long s_tris[kMaxBatchMaps];
+    __shared__ unsigned s_blocks[kMaxBatchMaps];
     for (int m = threadIdx.x; m < n; m += kThreads) {
         s_epoch[m] = maps[m].v.ctr->dirty_epoch;
         s_tris[m] = 0;
@@ -260,6 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
     }
     load_prefix(s_pre, ctl->pre_p, n);
     mesh_tables(S, false);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned counts;
     for (int it = 0;; ++it) {
         const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, false, S);
@@ -267,43 +271,43 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
         for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
             const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
             batch_lookup(maps, s_pre, n, S, j0, nb);
-            for (int j = 0; j < nb; ++j) {
+            for (int j = wave; j < nb; j += kThreads / 64) {
                 const int mi = S.mis[j];
-                mesh_stage<0>(maps[mi].v, S.nbs[j], S.h[0], threadIdx.x);
+                mesh_stage<1>(maps[mi].v, S.nbs[j], S.h[wave], lane);
                 const unsigned long long t =
-                    wave_sum_u64((unsigned long long)mesh_classify<0>(S.h[0], S.ntri, threadIdx.x, nullptr, &counts));
-                if ((threadIdx.x & 63) == 0) S.rcnt[threadIdx.x >> 6] = (long long)t;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    long long tot = 0;
-                    for (int w = 0; w < kThreads / 64; ++w) tot += S.rcnt[w];
-                    maps[mi].v.mesh_cnt[S.nbs[j][0]] = (uint16_t)tot;
-                    s_tris[mi] += tot;
-                    s_blocks[mi] += 1;
+                    wave_sum_u64((unsigned long long)mesh_classify<1>(S.h[wave], S.ntri, lane, nullptr, &counts));
+                wave_lds_sync();
+                if (lane == 0) {
+                    maps[mi].v.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
+                    atomicAdd(&s_tris[mi], t);
+                    atomicAdd(&s_blocks[mi], 1u);
                 }
-                __syncthreads();
             }
+            __syncthreads();  // the batch's lookups are rewritten by the next batch
         }
         __syncthreads();
     }
     for (int m = threadIdx.x; m < n; m += kThreads) {
-        scan.wg_tris[(size_t)blockIdx.x * n + m] = s_tris[m];
-        scan.wg_blocks[(size_t)blockIdx.x * n + m] = s_blocks[m];
+        scan.wg_tris[(size_t)blockIdx.x * n + m] = (long long)s_tris[m];
+        scan.wg_blocks[(size_t)blockIdx.x * n + m] = (int)s_blocks[m];
     }
 }
 
 // One workgroup per map: that map's offsets over the counting pass's workgroups.
-__global__ __launch_bounds__(kThreads) void k_batch_mesh_scan(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n, int G,
-                                                              int k)
+__global__ __launch_bounds__(kThreads) void k_batch_mesh_scan(BatchMap *maps, MeshScan scan, MeshReport *reports, int n,
+                                                              int G, int k)
 {
     const int m = blockIdx.x;
     const BatchMap &B = maps[m];
-    mesh_scan_map(B.v, 0, scan.wg_tris + m, scan.wg_blocks + m, scan.wg_off + m, G, k, n, B.out.cap, &ctl->tris[m]);
+    mesh_scan_map(B.v, 0, scan.wg_tris + m, scan.wg_blocks + m, scan.wg_off + m, G, k, n, B.out.cap, &reports[m]);
 }
 
+// One wavefront per block; a round takes up to four consecutive candidates of one map
+// (the list is in item order, so a map's blocks are consecutive), so that the round's
+// output is one contiguous range of that map's buffer.
 __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
 {
-    __shared__ MeshSmem<0, HaloFull> S;
+    __shared__ MeshSmem<1, HaloFull> S;
     __shared__ MeshStage st;
     __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ uint32_t s_epoch[kMaxBatchMaps];
@@ -315,33 +319,42 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
     load_prefix(s_pre, ctl->pre_p, n);
     mesh_tables(S, true);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned counts;
+    unsigned counts = 0;
     for (int it = 0;; ++it) {
         const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, true, S);
         if (cnt < 0) break;
         for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
             const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
             batch_lookup(maps, s_pre, n, S, j0, nb);
-            for (int j = 0; j < nb; ++j) {
-                const int mi = S.mis[j];
-                const BatchMap &B = maps[mi];
-                mesh_stage<0>(B.v, S.nbs[j], S.h[0], threadIdx.x);
-                if (threadIdx.x == 0) S.rbc[0] = S.bcs[j];
-                const int mine = mesh_classify<0>(S.h[0], S.ntri, threadIdx.x, S.ccase[0], &counts);
+            for (int r = 0; r < nb;) {
+                const int mr = S.mis[r];
+                int in_round = 1;
+                while (in_round < kThreads / 64 && r + in_round < nb && S.mis[r + in_round] == mr) ++in_round;
+                const int j = r + wave;
+                const bool has = wave < in_round;
+                const BatchMap &B = maps[mr];
+                int mine = 0;
+                if (has) {
+                    mesh_stage<1>(B.v, S.nbs[j], S.h[wave], lane);
+                    if (lane == 0) S.rbc[wave] = S.bcs[j];
+                    mine = mesh_classify<1>(S.h[wave], S.ntri, lane, S.ccase[wave], &counts);
+                }
                 const int incl = wave_scan_incl(mine);
                 if (lane == 63) S.rcnt[wave] = incl;
                 __syncthreads();
-                int woff = 0, tot = 0;
+                int woff = 0, rtot = 0;
 #pragma unroll
                 for (int w = 0; w < kThreads / 64; ++w) {
                     const int c = (int)S.rcnt[w];
                     woff += w < wave ? c : 0;
-                    tot += c;
+                    rtot += c;
                 }
-                const long long r0 = s_next[mi];
-                mesh_round_out<0>(B.v, S, st, true, 0, threadIdx.x, counts, woff + incl - mine, mine, tot, r0, B.out);
-                if (threadIdx.x == 0) s_next[mi] = r0 + tot;
+                const long long r0 = s_next[mr];
+                mesh_round_out<1>(B.v, S, st, has, wave, lane, counts, woff + incl - mine, mine, rtot, r0, B.out);
+                __syncthreads();  // every thread has read s_next[mr] and the round's counts
+                if (threadIdx.x == 0) s_next[mr] = r0 + rtot;
                 __syncthreads();
+                r += in_round;
             }
         }
         __syncthreads();
@@ -355,21 +368,18 @@ MeshGrid batch_mesh_grid()
     return cached;
 }
 
-hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan scan, int n_maps, int total_tiles,
-                        int schedule, int grid, hipStream_t s)
+hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan scan, MeshReport *reports,
+                        int n_maps, int total_tiles, int schedule, int grid, hipStream_t s)
 {
     const MeshGrid mg = batch_mesh_grid();
     if (total_tiles < 1 || grid < 1 || grid > kMaxMeshGrid) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batch_alloc, dim3(total_tiles), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
-    if (schedule == 0) {
-        hipLaunchKernelGGL(k_batch_tsdf<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
-        hipLaunchKernelGGL(k_batch_labels<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
-    } else {
-        hipLaunchKernelGGL(k_batch_tsdf<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
-        hipLaunchKernelGGL(k_batch_labels<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
-    }
+    if ((schedule & 1) == 0) hipLaunchKernelGGL(k_batch_tsdf<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
+    else hipLaunchKernelGGL(k_batch_tsdf<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, sync, n_maps);
+    if ((schedule & 2) == 0) hipLaunchKernelGGL(k_batch_labels<0>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
+    else hipLaunchKernelGGL(k_batch_labels<1>, dim3(grid), dim3(kThreads), 0, s, maps, ctl, n_maps);
     hipLaunchKernelGGL(k_batch_mesh_count, dim3(mg.count), dim3(kThreads), 0, s, maps, ctl, scan, n_maps);
-    hipLaunchKernelGGL(k_batch_mesh_scan, dim3(n_maps), dim3(kThreads), 0, s, maps, ctl, scan, n_maps, mg.emit,
+    hipLaunchKernelGGL(k_batch_mesh_scan, dim3(n_maps), dim3(kThreads), 0, s, maps, scan, reports, n_maps, mg.emit,
                        mg.count / mg.emit);
     hipLaunchKernelGGL(k_batch_mesh_emit, dim3(mg.emit), dim3(kThreads), 0, s, maps, ctl, scan, n_maps);
     return hipGetLastError();

@@ -20,9 +20,10 @@ __global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, Me
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_mesh_scan(MapView m, int mode, MeshScan scan, int G, int k, long long cap)
+__global__ __launch_bounds__(kThreads) void k_mesh_scan(MapView m, int mode, MeshScan scan, int G, int k, long long cap,
+                                                        MeshReport *report)
 {
-    mesh_scan_map(m, mode, scan.wg_tris, scan.wg_blocks, scan.wg_off, G, k, 1, cap, nullptr);
+    mesh_scan_map(m, mode, scan.wg_tris, scan.wg_blocks, scan.wg_off, G, k, 1, cap, report);
 }
 
 template <int kSched>
@@ -43,15 +44,15 @@ MeshGrid mesh_grid(int schedule)
     return cached[k];
 }
 
-hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, int schedule,
-                       MeshGrid grid, hipStream_t s)
+hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, MeshReport *report,
+                       int schedule, MeshGrid grid, hipStream_t s)
 {
     if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
         return hipErrorInvalidValue;
     const int k = grid.count / grid.emit;
     if (schedule == 0) hipLaunchKernelGGL(k_mesh_count<0>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
     else hipLaunchKernelGGL(k_mesh_count<1>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
-    hipLaunchKernelGGL(k_mesh_scan, dim3(1), dim3(kThreads), 0, s, m, mode, scan, grid.emit, k, out.cap);
+    hipLaunchKernelGGL(k_mesh_scan, dim3(1), dim3(kThreads), 0, s, m, mode, scan, grid.emit, k, out.cap, report);
     if (schedule == 0) hipLaunchKernelGGL(k_mesh_emit<0>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
     else hipLaunchKernelGGL(k_mesh_emit<1>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
     return hipGetLastError();

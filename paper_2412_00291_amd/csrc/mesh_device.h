@@ -421,7 +421,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
 // epoch recorded here.
 __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const long long *wg_tris,
                                               const int32_t *wg_blocks, long long *wg_off, int G, int k, int stride,
-                                              long long cap, unsigned long long *tris_out)
+                                              long long cap, MeshReport *report)
 {
     __shared__ long long s_part[kThreads / 64];
     __shared__ long long s_blk[kThreads / 64];
@@ -473,7 +473,11 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
         c->mesh_tris = (unsigned long long)total;
         c->mesh_blocks = (unsigned long long)blocks;
         if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
-        if (tris_out) *tris_out = (unsigned long long)total;
+        if (report) {  // host memory: system-scope stores, seen by the host after the kernel
+            __hip_atomic_store(&report->tris, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&report->blocks, (unsigned long long)blocks, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 

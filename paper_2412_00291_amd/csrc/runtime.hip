@@ -24,6 +24,9 @@ struct map_s {
     MapView v{};
     FrameView f{};
     Counters *h_ctr = nullptr;  // pinned mirror for read-back
+    MeshReport *h_report = nullptr;  // host-mapped, written by the extraction's scan kernel
+    MeshReport *d_report = nullptr;  // the same memory as seen by the device
+    hipEvent_t done = nullptr;       // recorded after an extraction, waited on by spinning
     hipStream_t last_stream = nullptr;
     bool has_scan = false;
     MeshScan scan{};        // extraction scratch, kMaxMeshGrid workgroups
@@ -70,6 +73,16 @@ static int fail(map_t *m, int code, const char *fmt, ...)
                         __LINE__);                                                                \
     } while (0)
 
+// Wait for an event by polling: a blocking wait can sleep, and waking costs more than
+// the frame's last kernels take.
+static hipError_t spin_wait(hipEvent_t e)
+{
+    for (;;) {
+        const hipError_t q = hipEventQuery(e);
+        if (q != hipErrorNotReady) return q;
+    }
+}
+
 static uint64_t next_pow2(uint64_t x)
 {
     uint64_t p = 1;
@@ -93,6 +106,8 @@ static void free_all(map_t *m)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (m->h_ctr) (void)hipHostFree(m->h_ctr);
+    if (m->h_report) (void)hipHostFree(m->h_report);
+    if (m->done) (void)hipEventDestroy(m->done);
 }
 
 // rigid transform check: finite, last row (0,0,0,1), orthonormal rotation to 1e-5, det > 0
@@ -238,6 +253,9 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&m->scan.wg_blocks, kMaxMeshGrid * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&m->scan.wg_off, kMaxMeshGrid * sizeof(long long)));
     CREATE_TRY(hipHostMalloc((void **)&m->h_ctr, sizeof(Counters), hipHostMallocDefault));
+    CREATE_TRY(hipHostMalloc((void **)&m->h_report, sizeof(MeshReport), hipHostMallocMapped | hipHostMallocCoherent));
+    CREATE_TRY(hipHostGetDevicePointer((void **)&m->d_report, m->h_report, 0));
+    CREATE_TRY(hipEventCreateWithFlags(&m->done, hipEventDisableTiming));
     CREATE_TRY(hipMemsetAsync(v.dw, 0, nb * kBlockVoxels * sizeof(float2), s));
     CREATE_TRY(hipMemsetAsync(v.counts, 0, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t), s));
     CREATE_TRY(hipMemsetAsync(v.coords, 0, nb * sizeof(int4), s));
@@ -461,11 +479,13 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     HIP_TRY(m, hipSetDevice(m->p.device));
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
     const MeshGrid grid = mesh_grid(m->sched[2]);
-    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] { return launch_mesh(m->v, mode, out, m->scan, m->sched[2], grid, s); }));
-    HIP_TRY(m, hipMemcpyAsync(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HIP_TRY(m, hipStreamSynchronize(s));
+    HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
+        return launch_mesh(m->v, mode, out, m->scan, m->d_report, m->sched[2], grid, s);
+    }));
+    HIP_TRY(m, hipEventRecord(m->done, s));
+    HIP_TRY(m, spin_wait(m->done));
     m->last_stream = s;
-    const int64_t n = (int64_t)m->h_ctr->mesh_tris;
+    const int64_t n = (int64_t)__atomic_load_n(&m->h_report->tris, __ATOMIC_ACQUIRE);
     *n_tris = n;
     if (n > cap_tris)
         return fail(m, MAP_ERR_BUFFER_TOO_SMALL, "extract_mesh: %lld triangles, capacity %lld", (long long)n,
@@ -670,6 +690,8 @@ struct map_batch_s {
     BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
     BatchSync *d_sync = nullptr;
     MeshScan scan{};  // [kMaxMeshGrid][kMaxBatchMaps]
+    MeshReport *h_reports = nullptr, *d_reports = nullptr;  // host-mapped, one per map of a step
+    hipEvent_t done = nullptr;
     int schedule = 0, grid = 2048;
     bool use_graph = true;
     // one executable graph per step shape (map count, tile count, schedule, grid, stream)
@@ -686,6 +708,8 @@ static void batch_free(map_batch_t *b)
     void *ptrs[] = {b->d_sync, b->scan.wg_tris, b->scan.wg_blocks, b->scan.wg_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (b->h_reports) (void)hipHostFree(b->h_reports);
+    if (b->done) (void)hipEventDestroy(b->done);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
 }
@@ -713,7 +737,11 @@ extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out
               hipMalloc(&b->scan.wg_blocks, (size_t)kMaxMeshGrid * kMaxBatchMaps * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&b->scan.wg_off, (size_t)kMaxMeshGrid * kMaxBatchMaps * sizeof(long long)) == hipSuccess &&
               hipHostMalloc((void **)&b->h_desc, kMaxBatchMaps * sizeof(BatchMap), hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void **)&b->h_reports, kMaxBatchMaps * sizeof(MeshReport),
+                            hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+              hipHostGetDevicePointer((void **)&b->d_reports, b->h_reports, 0) == hipSuccess &&
+              hipEventCreateWithFlags(&b->done, hipEventDisableTiming) == hipSuccess;
     if (ok) {
         std::memset(b->h_ctl, 0, sizeof(BatchCtl));
         ok = hipMemcpy(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice) == hipSuccess &&
@@ -730,7 +758,7 @@ extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out
 
 extern "C" int map_batch_configure(map_batch_t *b, int32_t schedule, int32_t grid, int32_t use_graph)
 {
-    if (!b || (schedule != 0 && schedule != 1) || grid < 64 || grid > kMaxMeshGrid) return MAP_ERR_INVALID_ARG;
+    if (!b || schedule < 0 || schedule > 3 || grid < 64 || grid > kMaxMeshGrid) return MAP_ERR_INVALID_ARG;
     b->schedule = schedule;
     b->grid = grid;
     b->use_graph = use_graph != 0;
@@ -819,7 +847,8 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
             hipGraphExec_t ge = nullptr;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return fail_b(e, "graph capture");
-            hipError_t le = launch_batch(b->d_desc, b->d_ctl, b->d_sync, b->scan, n, tiles, b->schedule, b->grid, s);
+            hipError_t le =
+                launch_batch(b->d_desc, b->d_ctl, b->d_sync, b->scan, b->d_reports, n, tiles, b->schedule, b->grid, s);
             e = hipStreamEndCapture(s, &g);
             if (le != hipSuccess) return fail_b(le, "batched launch");
             if (e != hipSuccess) return fail_b(e, "graph capture end");
@@ -831,17 +860,17 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         e = hipGraphLaunch(itg->second, s);
         if (e != hipSuccess) return fail_b(e, "graph launch");
     } else {
-        e = launch_batch(b->d_desc, b->d_ctl, b->d_sync, b->scan, n, tiles, b->schedule, b->grid, s);
+        e = launch_batch(b->d_desc, b->d_ctl, b->d_sync, b->scan, b->d_reports, n, tiles, b->schedule, b->grid, s);
         if (e != hipSuccess) return fail_b(e, "batched launch");
     }
-    e = hipMemcpyAsync(b->h_ctl->tris, b->d_ctl->tris, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return fail_b(e, "result read-back");
-    e = hipStreamSynchronize(s);
+    e = hipEventRecord(b->done, s);
+    if (e != hipSuccess) return fail_b(e, "step event");
+    e = spin_wait(b->done);
     if (e != hipSuccess) return fail_b(e, "step");
     int rc = MAP_OK;
     for (int i = 0; i < n; ++i) {
         map_t *m = b->maps[items[i].map_index];
-        const int64_t t = (int64_t)b->h_ctl->tris[i];
+        const int64_t t = (int64_t)__atomic_load_n(&b->h_reports[i].tris, __ATOMIC_ACQUIRE);
         n_tris[i] = t;
         m->has_scan = true;
         m->last_stream = s;

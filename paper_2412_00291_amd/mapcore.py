@@ -200,15 +200,16 @@ def map_integrate_labels_multi(handle, cams, labels_dev, T_wc, stream=None):
     n = len(cams)
     if len(labels_dev) != n or len(T_wc) != n:
         raise ValueError("cams, labels and poses differ in length")
-    carr = (_Camera * n)(*[c._c() for c in cams])
-    ptrs = (ctypes.c_void_p * n)()
-    for i, (c, l) in enumerate(zip(cams, labels_dev)):
+    carr = _cam_array(cams)
+    ptrs = np.empty(n, np.uint64)
+    for i in range(n):
+        c, l = cams[i], labels_dev[i]
         if l.numel() != c.width * c.height:
             raise ValueError("label image size does not match the camera model")
-        ptrs[i] = _dev(l, torch.uint8, "labels").value
-    T = np.ascontiguousarray(np.stack([np.asarray(t, np.float32).reshape(16) for t in T_wc]))
-    return _lib.map_integrate_labels_multi(handle, n, ctypes.cast(carr, _P), ctypes.cast(ptrs, _P),
-                                           T.ctypes.data, _stream(stream))
+        ptrs[i] = _dev_ptr(l, torch.uint8, "labels")
+    T = np.ascontiguousarray(np.asarray(T_wc, np.float32).reshape(n, 16))
+    return _lib.map_integrate_labels_multi(handle, n, ctypes.cast(carr, _P), ptrs.ctypes.data, T.ctypes.data,
+                                           _stream(stream))
 
 
 def map_extract_mesh(handle, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=None):
@@ -417,35 +418,83 @@ def map_batch_destroy(batch):
     _lib.map_batch_destroy(batch)
 
 
+_ITEM_DTYPE = np.dtype({"names": ["map_index", "lidar", "range_dev", "T_wl", "n_cams", "cams", "labels_dev", "T_wc",
+                                   "pos_dev", "lab_dev", "edge_keys_dev", "cap_tris"],
+                         "formats": [np.int32, np.uint64, np.uint64, np.uint64, np.int32, np.uint64, np.uint64,
+                                     np.uint64, np.uint64, np.uint64, np.uint64, np.int64],
+                         "offsets": [_BatchItem.map_index.offset, _BatchItem.lidar.offset,
+                                     _BatchItem.range_dev.offset, _BatchItem.T_wl.offset, _BatchItem.n_cams.offset,
+                                     _BatchItem.cams.offset, _BatchItem.labels_dev.offset, _BatchItem.T_wc.offset,
+                                     _BatchItem.pos_dev.offset, _BatchItem.lab_dev.offset,
+                                     _BatchItem.edge_keys_dev.offset, _BatchItem.cap_tris.offset],
+                         "itemsize": ctypes.sizeof(_BatchItem)})
+_cam_cache = {}
+
+
+def _cam_array(cams):
+    """ctypes camera array for a list of CameraModel (cached by value)."""
+    key = tuple((c.width, c.height, c.fx, c.fy, c.cx, c.cy) for c in cams)
+    arr = _cam_cache.get(key)
+    if arr is None:
+        arr = (_Camera * max(len(cams), 1))(*[c._c() for c in cams])
+        if len(_cam_cache) < 1024:
+            _cam_cache[key] = arr
+    return arr
+
+
+def _dev_ptr(t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        _dev(t, dtype, name)  # raises the specific error
+    return t.data_ptr()
+
+
 def map_batch_step(batch, items, stream=None):
     """items: list of dicts with map_index, lidar (LidarModel), range (device tensor), T_wl,
     and optionally cams (CameraModel list), labels (device tensors), T_wc (poses), pos, lab,
-    keys (mesh outputs).  Returns (status, [triangles per item])."""
+    keys (mesh outputs).  Returns (status, [triangles per item]).  The descriptors are
+    packed into one record array; poses and label pointers into one array each."""
     import torch
     n = len(items)
-    arr = (_BatchItem * n)()
-    keep = []
+    rec = np.zeros(n, _ITEM_DTYPE)
+    max_c = max((len(it.get("cams") or []) for it in items), default=0)
+    poses = np.empty((n, 16), np.float32)
+    cposes = np.zeros((n, max(max_c, 1), 16), np.float32)
+    lptrs = np.zeros((n, max(max_c, 1)), np.uint64)
+    keep = [rec, poses, cposes, lptrs]
     for i, it in enumerate(items):
         L = it["lidar"]._c()
-        T = np.ascontiguousarray(np.asarray(it["T_wl"], np.float32).reshape(16))
+        keep.append(L)
+        poses[i] = np.asarray(it["T_wl"], np.float32).reshape(16)
         cams = it.get("cams") or []
         nc = len(cams)
-        carr = (_Camera * max(nc, 1))(*[c._c() for c in cams])
-        ptrs = (ctypes.c_void_p * max(nc, 1))()
-        for c, l in enumerate(it.get("labels") or []):
-            ptrs[c] = _dev(l, torch.uint8, "labels").value
-        Tc = (np.ascontiguousarray(np.stack([np.asarray(t, np.float32).reshape(16) for t in it["T_wc"]]))
-              if nc else np.zeros(16, np.float32))
+        labels = it.get("labels") or []
+        if len(labels) != nc or len(it.get("T_wc") or []) != nc:
+            raise ValueError("cams, labels and poses differ in length")
+        carr = _cam_array(cams)
+        keep.append(carr)
+        for c in range(nc):
+            lptrs[i, c] = _dev_ptr(labels[c], torch.uint8, "labels")
+            cposes[i, c] = np.asarray(it["T_wc"][c], np.float32).reshape(16)
         pos, lab, keys = it.get("pos"), it.get("lab"), it.get("keys")
         cap = 0 if pos is None else pos.shape[0]
-        arr[i] = _BatchItem(int(it["map_index"]), ctypes.addressof(L), _dev(it["range"], torch.float32, "range").value,
-                            T.ctypes.data, nc, ctypes.addressof(carr), ctypes.addressof(ptrs), Tc.ctypes.data,
-                            _dev(pos, torch.float32, "pos").value if cap else None,
-                            _dev(lab, torch.uint8, "lab").value if cap else None,
-                            _dev(keys, torch.int64, "keys").value if (cap and keys is not None) else None, cap)
-        keep += [L, T, carr, ptrs, Tc]
+        r = rec[i]
+        r["map_index"] = int(it["map_index"])
+        r["lidar"] = ctypes.addressof(L)
+        r["range_dev"] = _dev_ptr(it["range"], torch.float32, "range")
+        r["n_cams"] = nc
+        r["cams"] = ctypes.addressof(carr)
+        if cap:
+            r["pos_dev"] = _dev_ptr(pos, torch.float32, "pos")
+            r["lab_dev"] = _dev_ptr(lab, torch.uint8, "lab")
+            if keys is not None:
+                r["edge_keys_dev"] = _dev_ptr(keys, torch.int64, "keys")
+        r["cap_tris"] = cap
+    rec["T_wl"] = poses.ctypes.data + 64 * np.arange(n, dtype=np.uint64)
+    rec["T_wc"] = cposes.ctypes.data + np.uint64(cposes.shape[1] * 64) * np.arange(n, dtype=np.uint64)
+    rec["labels_dev"] = lptrs.ctypes.data + np.uint64(lptrs.shape[1] * 8) * np.arange(n, dtype=np.uint64)
     out = np.zeros(n, np.int64)
-    st = _lib.map_batch_step(batch, ctypes.cast(arr, _P), n, out.ctypes.data, _stream(stream))
+    st = _lib.map_batch_step(batch, rec.ctypes.data, n, out.ctypes.data, _stream(stream))
+    del keep
     return st, out.tolist()
 
 

@@ -93,7 +93,7 @@ def _run_batched(torch, data, schedule, grid):
     return maps, batch, meshes
 
 
-@pytest.mark.parametrize("schedule,grid", [(0, 2048), (1, 1024)])
+@pytest.mark.parametrize("schedule,grid", [(0, 2048), (1, 1024), (2, 4096), (3, 1024)])
 def test_batched_equals_sequential(torch_dev_batch, batch_data, schedule, grid):
     torch = torch_dev_batch
     seq_maps, seq_meshes = _run_sequential(torch, batch_data)
