@@ -64,6 +64,7 @@ struct MapView {
     uint32_t *hframe;         // [hmask + 1] integration call that inserted the key (~0: none)
     uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
     uint16_t *mesh_cnt;       // [max_blocks] triangles of a block in the current extraction
+    int32_t *mesh_nbr;        // [max_blocks][8] slots of b + e, e in {0,1}^3 (-1: absent), same
     Counters *ctr;
     SyncState *sync;
     uint32_t hmask;
@@ -234,8 +235,12 @@ struct MeshGrid {
 };
 MeshGrid mesh_grid(int schedule);
 MeshGrid batch_mesh_grid();
-hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, MeshReport *report,
-                       int schedule, MeshGrid grid, hipStream_t s);
+// Meshing is the counting pass, then the scan and the emitting pass (which may run on
+// another stream once the counting pass is done).
+hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, int schedule, MeshGrid grid,
+                             hipStream_t s);
+hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan,
+                              MeshReport *report, int schedule, MeshGrid grid, hipStream_t s);
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
                         uint8_t *valid, hipStream_t s);
 hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,

@@ -208,8 +208,9 @@ __device__ __forceinline__ int batch_candidates(const BatchMap *maps, const int 
     if (item < total) {
         const int mi = find_map(s_pre, n, (int)item);
         const MapView &v = maps[mi].v;
-        take = v.dirty_flag[item - s_pre[mi]] == s_epoch[mi];
-        if (need_tris && take) take = v.mesh_cnt[item - s_pre[mi]] != 0;
+        const uint32_t fl = v.dirty_flag[item - s_pre[mi]];
+        const uint16_t nt = need_tris ? v.mesh_cnt[item - s_pre[mi]] : (uint16_t)1;
+        take = fl == s_epoch[mi] && nt != 0;
     }
     const unsigned long long bal = __ballot(take);
     if (lane == 0) S.wcnt[wave] = __popcll(bal);
@@ -229,7 +230,8 @@ __device__ __forceinline__ int batch_candidates(const BatchMap *maps, const int 
 // Map, coordinates and neighbour slots of list entries j0 .. j0 + nb - 1 (as
 // mesh_batch_lookup, the map resolved per entry).
 template <class Smem>
-__device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_pre, int n, Smem &S, int j0, int nb)
+__device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_pre, int n, Smem &S, int j0, int nb,
+                                             bool fetch)
 {
     const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
     if (jb < nb) {
@@ -237,12 +239,18 @@ __device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_
         const int mi = find_map(s_pre, n, item);
         const MapView &v = maps[mi].v;
         const int slot = item - s_pre[mi];
-        const int4 bc = v.coords[slot];
-        if (e == 0) {
-            S.bcs[jb] = bc;
-            S.mis[jb] = mi;
+        int s;
+        if (fetch) {
+            s = v.mesh_nbr[(size_t)slot * 8 + e];
+            if (e == 0) S.bcs[jb] = v.coords[slot];
+        } else {
+            const int4 bc = v.coords[slot];
+            if (e == 0) S.bcs[jb] = bc;
+            s = e == 0 ? slot : hash_find(v, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
+            v.mesh_nbr[(size_t)slot * 8 + e] = s;
         }
-        S.nbs[jb][e] = e == 0 ? slot : hash_find(v, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
+        if (e == 0) S.mis[jb] = mi;
+        S.nbs[jb][e] = s;
     }
     __syncthreads();
 }
@@ -270,7 +278,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
         if (cnt < 0) break;
         for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
             const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
-            batch_lookup(maps, s_pre, n, S, j0, nb);
+            batch_lookup(maps, s_pre, n, S, j0, nb, false);
             for (int j = wave; j < nb; j += kThreads / 64) {
                 const int mi = S.mis[j];
                 mesh_stage<1>(maps[mi].v, S.nbs[j], S.h[wave], lane);
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
         if (cnt < 0) break;
         for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
             const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
-            batch_lookup(maps, s_pre, n, S, j0, nb);
+            batch_lookup(maps, s_pre, n, S, j0, nb, true);
             for (int r = 0; r < nb;) {
                 const int mr = S.mis[r];
                 int in_round = 1;

@@ -44,14 +44,22 @@ MeshGrid mesh_grid(int schedule)
     return cached[k];
 }
 
-hipError_t launch_mesh(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan, MeshReport *report,
-                       int schedule, MeshGrid grid, hipStream_t s)
+hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, int schedule, MeshGrid grid,
+                             hipStream_t s)
+{
+    if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
+        return hipErrorInvalidValue;
+    if (schedule == 0) hipLaunchKernelGGL(k_mesh_count<0>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
+    else hipLaunchKernelGGL(k_mesh_count<1>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
+    return hipGetLastError();
+}
+
+hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan,
+                              MeshReport *report, int schedule, MeshGrid grid, hipStream_t s)
 {
     if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
         return hipErrorInvalidValue;
     const int k = grid.count / grid.emit;
-    if (schedule == 0) hipLaunchKernelGGL(k_mesh_count<0>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
-    else hipLaunchKernelGGL(k_mesh_count<1>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
     hipLaunchKernelGGL(k_mesh_scan, dim3(1), dim3(kThreads), 0, s, m, mode, scan, grid.emit, k, out.cap, report);
     if (schedule == 0) hipLaunchKernelGGL(k_mesh_emit<0>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
     else hipLaunchKernelGGL(k_mesh_emit<1>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);

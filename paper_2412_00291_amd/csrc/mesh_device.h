@@ -33,7 +33,7 @@ constexpr int kMeshBatch = kThreads / 8;
 // counts.
 constexpr int kTriRow = 3 * MC_MAX_TRIS;
 template <int kSched, class Halo>
-struct MeshSmem {
+struct __align__(16) MeshSmem {
     uint8_t ntri[256];
     int8_t tris[sizeof(Halo) == sizeof(HaloFull) ? 256 * kTriRow : 4];
     Halo h[kSched == 0 ? 1 : kThreads / 64];
@@ -47,14 +47,20 @@ struct MeshSmem {
     long long rcnt[kThreads / 64];
 };
 
-// Copy the case tables into the workgroup's LDS (every thread; a barrier follows).
+// Copy the case tables into the workgroup's LDS with dword loads (every thread).  No
+// barrier of its own: the candidate scan that follows has barriers before any cube is
+// classified, and the table loads overlap its loads.
 template <class Smem>
 __device__ __forceinline__ void mesh_tables(Smem &S, bool with_tris)
 {
-    for (int i = threadIdx.x; i < 256; i += kThreads) S.ntri[i] = MC_NTRI[i];
-    if (with_tris)
-        for (int i = threadIdx.x; i < 256 * kTriRow; i += kThreads) S.tris[i] = MC_TRIS[i / kTriRow][i % kTriRow];
-    __syncthreads();
+    const uint32_t *ntri = reinterpret_cast<const uint32_t *>(MC_NTRI);
+    uint32_t *ntri_s = reinterpret_cast<uint32_t *>(S.ntri);
+    for (int i = threadIdx.x; i < 256 / 4; i += kThreads) ntri_s[i] = ntri[i];
+    if (with_tris) {
+        const uint32_t *tris = reinterpret_cast<const uint32_t *>(MC_TRIS);
+        uint32_t *tris_s = reinterpret_cast<uint32_t *>(S.tris);
+        for (int i = threadIdx.x; i < 256 * kTriRow / 4; i += kThreads) tris_s[i] = tris[i];
+    }
 }
 
 __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
@@ -67,16 +73,26 @@ __device__ __forceinline__ void worker_sync()
 }
 
 // Coordinates and neighbour slots (b + e, e in {0,1}^3; -1 when absent) of list entries
-// j0 .. j0 + nb - 1, nb <= kMeshBatch; every thread calls it.
+// j0 .. j0 + nb - 1, nb <= kMeshBatch; every thread calls it.  The counting pass looks the
+// neighbours up in the hash and keeps them in mesh_nbr for the emitting pass, which
+// fetches them with one coalesced read per block.
 template <class Smem>
-__device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int j0, int nb)
+__device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int j0, int nb, bool fetch)
 {
     const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
     if (jb < nb) {
         const int slot = S.list[j0 + jb];
-        const int4 bc = m.coords[slot];
-        if (e == 0) S.bcs[jb] = bc;
-        S.nbs[jb][e] = e == 0 ? slot : hash_find(m, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
+        int s;
+        if (fetch) {
+            s = m.mesh_nbr[(size_t)slot * 8 + e];
+            if (e == 0) S.bcs[jb] = m.coords[slot];
+        } else {
+            const int4 bc = m.coords[slot];
+            if (e == 0) S.bcs[jb] = bc;
+            s = e == 0 ? slot : hash_find(m, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
+            m.mesh_nbr[(size_t)slot * 8 + e] = s;
+        }
+        S.nbs[jb][e] = s;
     }
     __syncthreads();
 }
@@ -279,8 +295,12 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
     if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= nslots) return -1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long slot = ((long long)it * kThreads + threadIdx.x) * gridDim.x + blockIdx.x;
-    bool take = slot < nslots && (all || m.dirty_flag[slot] == epoch);
-    if (need_tris && take) take = m.mesh_cnt[slot] != 0;
+    bool take = false;
+    if (slot < nslots) {  // both loads issued together (the count is only used for dirty slots)
+        const uint32_t fl = all ? epoch : m.dirty_flag[slot];
+        const uint16_t nt = need_tris ? m.mesh_cnt[slot] : (uint16_t)1;
+        take = fl == epoch && nt != 0;
+    }
     const unsigned long long bal = __ballot(take);
     if (lane == 0) S.wcnt[wave] = __popcll(bal);
     __syncthreads();
@@ -311,7 +331,7 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
-            mesh_batch_lookup(m, S, j0, nb);
+            mesh_batch_lookup(m, S, j0, nb, false);
             if (kSched == 0) {
                 for (int j = 0; j < nb; ++j) {
                     mesh_stage<0>(m, S.nbs[j], S.h[0], threadIdx.x);
@@ -385,7 +405,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
-            mesh_batch_lookup(m, S, j0, nb);
+            mesh_batch_lookup(m, S, j0, nb, true);
             for (int r = 0; r < nb; r += kPerRound) {
                 const int j = r + worker;
                 const bool has = j < nb;

@@ -100,7 +100,7 @@ static void free_all(map_t *m)
     m->prof_pending.clear();
     m->prof_free.clear();
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.hframe,
-                    m->v.dirty_flag, m->v.mesh_cnt, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
+                    m->v.dirty_flag, m->v.mesh_cnt, m->v.mesh_nbr, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->lut_buf, m->partial, m->scan.wg_tris, m->scan.wg_blocks,
                     m->scan.wg_off};
     for (void *p : ptrs)
@@ -247,6 +247,7 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&v.hframe, hcap * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.dirty_flag, nb * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.mesh_cnt, nb * sizeof(uint16_t)));
+    CREATE_TRY(hipMalloc(&v.mesh_nbr, nb * 8 * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&v.ctr, sizeof(Counters)));
     CREATE_TRY(hipMalloc(&v.sync, sizeof(SyncState)));
     CREATE_TRY(hipMalloc(&m->scan.wg_tris, kMaxMeshGrid * sizeof(long long)));
@@ -480,7 +481,8 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
     const MeshGrid grid = mesh_grid(m->sched[2]);
     HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
-        return launch_mesh(m->v, mode, out, m->scan, m->d_report, m->sched[2], grid, s);
+        hipError_t e = launch_mesh_count(m->v, mode, m->scan, m->sched[2], grid, s);
+        return e != hipSuccess ? e : launch_mesh_finish(m->v, mode, out, m->scan, m->d_report, m->sched[2], grid, s);
     }));
     HIP_TRY(m, hipEventRecord(m->done, s));
     HIP_TRY(m, spin_wait(m->done));
