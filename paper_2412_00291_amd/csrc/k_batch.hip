@@ -281,9 +281,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
             batch_lookup(maps, s_pre, n, S, j0, nb, false);
             for (int j = wave; j < nb; j += kThreads / 64) {
                 const int mi = S.mis[j];
-                mesh_stage<1>(maps[mi].v, S.nbs[j], S.h[wave], lane);
+                mesh_stage_rows<false>(maps[mi].v, S.nbs[j], S.h[wave], lane);
                 const unsigned long long t =
-                    wave_sum_u64((unsigned long long)mesh_classify<1>(S.h[wave], S.ntri, lane, nullptr, &counts));
+                    wave_sum_u64((unsigned long long)mesh_classify_rows(S.h[wave], S.ntri, lane, nullptr, &counts));
                 wave_lds_sync();
                 if (lane == 0) {
                     maps[mi].v.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
@@ -343,9 +343,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
                 const BatchMap &B = maps[mr];
                 int mine = 0;
                 if (has) {
-                    mesh_stage<1>(B.v, S.nbs[j], S.h[wave], lane);
+                    mesh_stage_rows<true>(B.v, S.nbs[j], S.h[wave], lane);
                     if (lane == 0) S.rbc[wave] = S.bcs[j];
-                    mine = mesh_classify<1>(S.h[wave], S.ntri, lane, S.ccase[wave], &counts);
+                    mine = mesh_classify_rows(S.h[wave], S.ntri, lane, S.ccase[wave], &counts);
                 }
                 const int incl = wave_scan_incl(mine);
                 if (lane == 63) S.rcnt[wave] = incl;

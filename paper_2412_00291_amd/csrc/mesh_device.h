@@ -13,13 +13,19 @@ namespace mc {
 
 // A staged halo: per voxel a code byte (bit 0: D < 0, bit 1: W > 0) for the cube cases;
 // the emitting pass also keeps D and the fused label for the vertices.
+// The wavefront schedule stages the halo by x-rows instead: rows[y + 9 z] holds the sign
+// bits (bits 0-8, D < 0) and observed bits (bits 16-24, W > 0) of the 9 voxels of row
+// (y, z), so a cube's case comes from four row words.
+constexpr int kHaloRows = kHalo * kHalo;
 struct HaloCode {
     uint8_t code[kHaloVoxels];
+    uint32_t rows[kHaloRows];
 };
 struct HaloFull {
     float d[kHaloVoxels];
     uint8_t code[kHaloVoxels];
     uint8_t fused[kHaloVoxels];
+    uint32_t rows[kHaloRows];
 };
 
 // Candidates are meshed in batches of kMeshBatch blocks; a batch's block coordinates and
@@ -142,6 +148,91 @@ __device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, Halo
 // packs each cube's triangle count into 4 bits of *counts, and stores each cube's case
 // in ccase[cube] when ccase is given.  A cube counts only when all eight corners are
 // observed (W > 0).
+// Stage a halo by rows (one wavefront): lane l takes rows l and l + 64.  A row's 8
+// voxels of one block are 64 contiguous bytes (four 16-byte loads), the 9th is the first
+// voxel of the +x neighbour's row.  With kFull the row's D values and fused labels are
+// staged too (halo index x + 9 row).
+template <bool kFull, class Halo>
+__device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb, Halo &S, int lane)
+{
+    for (int r = lane; r < kHaloRows; r += 64) {
+        const int y = r % kHalo, z = r / kHalo;
+        const int jj = ((y >> 3) << 1) | ((z >> 3) << 2);
+        const int s0 = nb[jj], s1 = nb[jj | 1];
+        const int off = 8 * (y & 7) + 64 * (z & 7);
+        uint32_t sign = 0, obs = 0;
+        float d[kHalo];
+        uint8_t fu[kHalo];
+#pragma unroll
+        for (int x = 0; x < kHalo; ++x) {
+            d[x] = 0.0f;
+            fu[x] = 255;
+        }
+        if (s0 >= 0) {
+            const float4 *p = reinterpret_cast<const float4 *>(m.dw + (size_t)s0 * kBlockVoxels + off);
+            float4 q[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) q[i] = p[i];
+            unsigned long long f8 = 0;
+            if constexpr (kFull)
+                f8 = *reinterpret_cast<const unsigned long long *>(m.fused + (size_t)s0 * kBlockVoxels + off);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float D0 = q[i].x, W0 = q[i].y, D1 = q[i].z, W1 = q[i].w;
+                sign |= (D0 < 0.0f ? 1u : 0u) << (2 * i) | (D1 < 0.0f ? 1u : 0u) << (2 * i + 1);
+                obs |= (W0 > 0.0f ? 1u : 0u) << (2 * i) | (W1 > 0.0f ? 1u : 0u) << (2 * i + 1);
+                d[2 * i] = D0;
+                d[2 * i + 1] = D1;
+            }
+#pragma unroll
+            for (int x = 0; x < 8; ++x) fu[x] = (uint8_t)(f8 >> (8 * x));
+        }
+        if (s1 >= 0) {
+            const size_t vi = (size_t)s1 * kBlockVoxels + off;
+            const float2 v = m.dw[vi];
+            sign |= (v.x < 0.0f ? 1u : 0u) << 8;
+            obs |= (v.y > 0.0f ? 1u : 0u) << 8;
+            d[8] = v.x;
+            if constexpr (kFull) fu[8] = m.fused[vi];
+        }
+        S.rows[r] = sign | (obs << 16);
+        if constexpr (kFull) {
+#pragma unroll
+            for (int x = 0; x < kHalo; ++x) {
+                S.d[kHalo * r + x] = d[x];
+                S.fused[kHalo * r + x] = fu[x];
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
+// Cases of the lane's 8 cubes, the x-row (cy, cz) = (lane % 8, lane / 8): cube cx has
+// index cx + 8 lane.  Returns the lane's triangles, packs each cube's count into 4 bits of
+// *counts (cube cx in nibble cx) and stores its case in ccase when given.
+template <class Halo>
+__device__ __forceinline__ int mesh_classify_rows(const Halo &S, const uint8_t *ntri, int lane, uint8_t *ccase,
+                                                  unsigned *counts)
+{
+    const int cy = lane & 7, cz = lane >> 3;
+    const uint32_t r00 = S.rows[cy + kHalo * cz], r10 = S.rows[cy + 1 + kHalo * cz];
+    const uint32_t r01 = S.rows[cy + kHalo * (cz + 1)], r11 = S.rows[cy + 1 + kHalo * (cz + 1)];
+    int mine = 0;
+    unsigned packed = 0;
+#pragma unroll
+    for (int cx = 0; cx < 8; ++cx) {
+        const uint32_t k = ((r00 >> cx) & 3u) | (((r10 >> cx) & 3u) << 2) | (((r01 >> cx) & 3u) << 4) |
+                           (((r11 >> cx) & 3u) << 6);
+        const uint32_t v = (r00 >> (16 + cx)) & (r10 >> (16 + cx)) & (r01 >> (16 + cx)) & (r11 >> (16 + cx)) & 3u;
+        const int nt = v == 3u ? (int)ntri[k] : 0;
+        if (ccase) ccase[cx + 8 * lane] = (uint8_t)k;
+        packed |= (unsigned)nt << (4 * cx);
+        mine += nt;
+    }
+    *counts = packed;
+    return mine;
+}
+
 template <int kSched, class Halo>
 __device__ __forceinline__ int mesh_classify(const Halo &S, const uint8_t *ntri, int rank, uint8_t *ccase,
                                              unsigned *counts)
@@ -195,7 +286,7 @@ __device__ __forceinline__ void mesh_desc(int worker, int rank, unsigned counts,
 #pragma unroll
     for (int it = 0; it < kCubes; ++it) {
         const int nt = (counts >> (4 * it)) & 15;
-        const int cube = it * kWidth + rank;
+        const int cube = kSched == 0 ? it * kWidth + rank : it + 8 * rank;  // the rows' cube order
         for (int q = 0; q < nt; ++q, ++r)
             if (r >= w0 && r < w0 + kStageTris) st.desc[r - w0] = (uint16_t)((worker << 12) | (cube << 3) | q);
     }
@@ -350,9 +441,9 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
                 my_blocks += nb;
             } else {
                 for (int j = wave; j < nb; j += kThreads / 64) {
-                    mesh_stage<1>(m, S.nbs[j], S.h[wave], lane);
+                    mesh_stage_rows<false>(m, S.nbs[j], S.h[wave], lane);
                     const unsigned long long t =
-                        wave_sum_u64((unsigned long long)mesh_classify<1>(S.h[wave], S.ntri, lane, nullptr, &counts));
+                        wave_sum_u64((unsigned long long)mesh_classify_rows(S.h[wave], S.ntri, lane, nullptr, &counts));
                     wave_lds_sync();
                     if (lane == 0) {
                         m.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
@@ -410,10 +501,14 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
                 const int j = r + worker;
                 const bool has = j < nb;
                 int mine = 0;
-                if (kSched == 0 || has) {
-                    mesh_stage<kSched>(m, S.nbs[j], S.h[worker], rank);
-                    if (rank == 0) S.rbc[worker] = S.bcs[j];
-                    mine = mesh_classify<kSched>(S.h[worker], S.ntri, rank, S.ccase[worker], &counts);
+                if (kSched == 0) {
+                    mesh_stage<0>(m, S.nbs[j], S.h[0], rank);
+                    if (rank == 0) S.rbc[0] = S.bcs[j];
+                    mine = mesh_classify<0>(S.h[0], S.ntri, rank, S.ccase[0], &counts);
+                } else if (has) {
+                    mesh_stage_rows<true>(m, S.nbs[j], S.h[worker], lane);
+                    if (lane == 0) S.rbc[worker] = S.bcs[j];
+                    mine = mesh_classify_rows(S.h[worker], S.ntri, lane, S.ccase[worker], &counts);
                 }
                 const int incl = wave_scan_incl(mine);
                 if (lane == 63) S.rcnt[wave] = incl;
