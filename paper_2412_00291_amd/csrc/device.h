@@ -599,7 +599,56 @@ __device__ __forceinline__ void close_frame_wave(const MapView &m, const FrameSt
 
 // Called only for band voxels of the last frame; a band voxel was updated by that frame,
 // so its weight is positive and the W > 0 condition of the label update holds without a
-// read of W.
+// read of W.  The votes of the call's cameras apply in camera order; the lane first
+// issues every camera's label read, then every count it needs (each camera's label and
+// the fused label), applies the votes in registers (cameras voting the same label share
+// the count), and writes each changed count once.
+// Band voxels of a touched block, compacted: load the block's 8 band words and their
+// prefix popcounts; band_select gives the voxel of the t-th set bit.
+struct BandWords {
+    unsigned long long w[8];
+    int pre[9];
+};
+
+__device__ __forceinline__ BandWords band_words(const FrameView &f, int e)
+{
+    BandWords b;
+    b.pre[0] = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        b.w[k] = f.band[(size_t)e * 8 + k];
+        b.pre[k + 1] = b.pre[k] + __popcll(b.w[k]);
+    }
+    return b;
+}
+
+__device__ __forceinline__ int band_select(const BandWords &b, int t)
+{
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) k += b.pre[j] <= t ? 1 : 0;
+    unsigned long long x = b.w[0];  // selects, not indexing: the arrays stay in registers
+    int pk = 0;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+        x = k == j ? b.w[j] : x;
+        pk = k == j ? b.pre[j] : pk;
+    }
+    int r = t - pk, pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {  // r-th set bit of x
+        const int c = __popcll(x & ((1ull << width) - 1ull));
+        if (r >= c) {
+            r -= c;
+            x >>= width;
+            pos += width;
+        }
+    }
+    return 64 * k + pos;
+}
+
+constexpr int kCamChunk = 4;  // cameras whose votes one pass gathers (register budget)
+
 __device__ __forceinline__ int label_voxel(const MapView &m, const CameraSet &cs, int slot, int3 bc, int li)
 {
     const size_t vi = (size_t)slot * kBlockVoxels + li;
@@ -609,30 +658,68 @@ __device__ __forceinline__ int label_voxel(const MapView &m, const CameraSet &cs
     const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
     uint16_t *cnt = m.counts + (size_t)slot * L * kBlockVoxels + li;
     int fl = m.fused[vi];
-    const int fl0 = fl;
+    const int fl_in = fl;
     int votes = 0;
-    for (int ci = 0; ci < cs.n; ++ci) {
-        const Pose &T = cs.T[ci];
-        const Camera &cam = cs.cam[ci];
-        const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
-        const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
-        const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
-        const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
-        if (!(pz > 0.0f)) continue;
-        const float u = cam.fx * (px / pz) + cam.cx;
-        const float v = cam.fy * (py / pz) + cam.cy;
-        if (!(u >= 0.0f && u < (float)cam.width && v >= 0.0f && v < (float)cam.height)) continue;
-        const int iu = (int)u, iv = (int)v;
-        const int l = cs.img[ci][(size_t)iv * cam.width + iu];
-        if (l >= L) continue;
-        unsigned cl = cnt[(size_t)l * kBlockVoxels];
-        if (cl < 65535u) cl++;
-        cnt[(size_t)l * kBlockVoxels] = (uint16_t)cl;
-        const unsigned cf = fl == 255 ? 0u : cnt[(size_t)fl * kBlockVoxels];
-        if (l != fl && (cl > cf || (cl == cf && l < fl))) fl = l;
-        votes++;
+    for (int base = 0; base < cs.n; base += kCamChunk) {  // chunks in camera order
+        int lab[kCamChunk];
+#pragma unroll
+        for (int k = 0; k < kCamChunk; ++k) {
+            lab[k] = -1;
+            const int ci = base + k;
+            if (ci >= cs.n) continue;
+            const Pose &T = cs.T[ci];
+            const Camera &cam = cs.cam[ci];
+            const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
+            const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
+            const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
+            const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
+            if (!(pz > 0.0f)) continue;
+            const float u = cam.fx * (px / pz) + cam.cx;
+            const float v = cam.fy * (py / pz) + cam.cy;
+            if (!(u >= 0.0f && u < (float)cam.width && v >= 0.0f && v < (float)cam.height)) continue;
+            lab[k] = cs.img[ci][(size_t)(int)v * cam.width + (int)u];
+        }
+        unsigned c0[kCamChunk];  // count of each camera's label before this chunk
+#pragma unroll
+        for (int k = 0; k < kCamChunk; ++k) {
+            if (lab[k] >= L) lab[k] = -1;
+            c0[k] = lab[k] >= 0 ? cnt[(size_t)lab[k] * kBlockVoxels] : 0u;
+        }
+        const int flc = fl;
+        const unsigned cf0 = flc == 255 ? 0u : cnt[(size_t)flc * kBlockVoxels];
+        unsigned cn[kCamChunk];  // count of camera k's label right after its vote
+#pragma unroll
+        for (int k = 0; k < kCamChunk; ++k) {
+            cn[k] = 0;
+            const int l = lab[k];
+            if (l < 0) continue;
+            unsigned cl = c0[k];
+#pragma unroll
+            for (int p = 0; p < k; ++p)
+                if (lab[p] == l) cl = cn[p];  // latest earlier vote for the same label
+            if (cl < 65535u) cl++;
+            cn[k] = cl;
+            unsigned cf = 0;
+            if (fl != 255) {
+                cf = fl == flc ? cf0 : 0u;
+#pragma unroll
+                for (int p = 0; p <= k; ++p)
+                    if (lab[p] == fl) cf = cn[p];
+            }
+            if (l != fl && (cl > cf || (cl == cf && l < fl))) fl = l;
+            votes++;
+        }
+#pragma unroll
+        for (int k = 0; k < kCamChunk; ++k) {
+            if (lab[k] < 0) continue;
+            bool last = true;  // the last vote for this label writes its count
+#pragma unroll
+            for (int q = k + 1; q < kCamChunk; ++q)
+                if (lab[q] == lab[k]) last = false;
+            if (last) cnt[(size_t)lab[k] * kBlockVoxels] = (uint16_t)cn[k];
+        }
     }
-    if (fl != fl0) m.fused[vi] = (uint8_t)fl;
+    if (fl != fl_in) m.fused[vi] = (uint8_t)fl;
     return votes;
 }
 

@@ -174,13 +174,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_labels(BatchMap *maps, Batch
         const int slot = B.f.tk_slot[e];
         const int3 bc = unpack_key(B.f.tk_key[e]);
         unsigned long long v = 0;
-#pragma unroll
-        for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
-            const int li = it * kWidth + rank;
-            const unsigned long long bits = B.f.band[(size_t)e * 8 + (li >> 6)];
-            if (bits == 0) continue;  // wave-uniform
-            if ((bits >> (li & 63)) & 1ull) v += label_voxel(B.v, B.cams, slot, bc, li);
-        }
+        const BandWords bw = band_words(B.f, e);
+        for (int t = rank; t < bw.pre[8]; t += kWidth) v += label_voxel(B.v, B.cams, slot, bc, band_select(bw, t));
         v = wave_sum_u64(v);
         if (lane == 0 && v) atomicAdd(&s_votes[mi], v);
     }

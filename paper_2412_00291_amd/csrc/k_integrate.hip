@@ -164,7 +164,8 @@ hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut
 
 // ---------------------------------------------------------------------------------
 // label fusion over the last frame's touched blocks, every camera of the call in order
-// (equal to one call per camera: a voxel's votes are sequential); schedules as above
+// (equal to one call per camera: a voxel's votes are sequential); a worker takes a block's
+// band voxels compacted (about one in ten voxels is in the band); schedules as above
 // ---------------------------------------------------------------------------------
 
 template <int kSched>
@@ -181,13 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
     for (int e = first; e < n; e += stride) {
         const int slot = f.tk_slot[e];
         const int3 bc = unpack_key(f.tk_key[e]);
-#pragma unroll
-        for (int it = 0; it < kBlockVoxels / kWidth; ++it) {
-            const int li = it * kWidth + rank;
-            const unsigned long long bits = f.band[(size_t)e * 8 + (li >> 6)];
-            if (bits == 0) continue;  // wave-uniform: one word per wave
-            if ((bits >> (li & 63)) & 1ull) my_votes += label_voxel(m, cs, slot, bc, li);
-        }
+        const BandWords b = band_words(f, e);
+        for (int t = rank; t < b.pre[8]; t += kWidth) my_votes += label_voxel(m, cs, slot, bc, band_select(b, t));
     }
     unsigned long long w = wave_sum_u64(my_votes);
     if (lane == 0) s_sum[wave] = w;
