@@ -28,6 +28,11 @@ if not os.path.exists(_LIB_FILE):
     raise ImportError(f"mapcore HIP library not built: {_LIB_FILE} is missing "
                       "(run `python -c 'import __graft_entry__ as g; g.build()'` from the repo root)")
 
+# torch first: the library then binds to the HIP runtime torch ships (same soname), so
+# torch's tensors and streams and this library share one runtime whatever the caller
+# imported first.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(_LIB_FILE)
 
 
