@@ -124,9 +124,11 @@ int map_integrate_labels_multi(map_t *map, int32_t n, const camera_model *cams,
  * Outputs (device): pos [cap_tris][3][3] float, lab [cap_tris][3] uint8, and, if
  * non-NULL, edge_keys [cap_tris][3] int64 (the voxel v and axis of each vertex's edge:
  * ((vx + 2^19) << 42) | ((vy + 2^19) << 22) | ((vz + 2^19) << 2) | axis).
- * Synchronises `stream` and writes the triangle count to the host *n_tris.  If it
- * exceeds cap_tris, only cap_tris triangles are written, MAP_ERR_BUFFER_TOO_SMALL is
- * returned and the dirty set is kept.  DIRTY mode clears the dirty set on success. */
+ * Writes the triangle count to the host *n_tris: the call returns as soon as the count
+ * is known, while the triangles are still being written on `stream`, so order any use
+ * of the outputs after it on that stream (or synchronise it).  If the count exceeds
+ * cap_tris, only cap_tris triangles are written, MAP_ERR_BUFFER_TOO_SMALL is returned
+ * and the dirty set is kept.  DIRTY mode clears the dirty set on success. */
 int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
                      int64_t *edge_keys_dev, int64_t cap_tris, int64_t *n_tris, void *stream);
 
@@ -160,7 +162,8 @@ int map_sdf_pose_adjoint(map_t *map, const float *xi_dev, const float *pts_dev, 
  * call.  n_tris [n_items] (host) receives each map's triangle count.  Returns MAP_OK,
  * MAP_ERR_BUFFER_TOO_SMALL if any map's output was too small (that map keeps its dirty
  * set), or an argument/device error; capacity rejections are reported per map by
- * map_sync.  Synchronises `stream`. */
+ * map_sync.  Returns when every map's triangle count is known; the outputs are written
+ * on `stream` after that, as with map_extract_mesh. */
 typedef struct map_batch_s map_batch_t;
 typedef struct {
     int32_t map_index;

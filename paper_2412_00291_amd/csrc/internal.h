@@ -27,7 +27,7 @@ struct Counters {
     int32_t last_touched;  // |T_k| of the last accepted frame (labels read it)
     int32_t last_new;
     int32_t overflow;      // touched list overflow (cannot happen with the sizing rule)
-    int32_t pad;
+    uint32_t extractions;  // extractions whose totals have been reported
 };
 
 // Same-address device atomics are serialised (about 12 ns apart on gfx950), so a value
@@ -88,6 +88,7 @@ struct MeshScan {
 struct MeshReport {
     unsigned long long tris;
     unsigned long long blocks;
+    unsigned long long seq;  // the map's extraction number, stored last (release)
 };
 
 // Per-frame scratch: frame set (de-duplication of the frame's blocks) and touched list.

@@ -588,10 +588,14 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
         c->mesh_tris = (unsigned long long)total;
         c->mesh_blocks = (unsigned long long)blocks;
         if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
-        if (report) {  // host memory: system-scope stores, seen by the host after the kernel
+        const uint32_t seq = c->extractions + 1;
+        c->extractions = seq;
+        if (report) {  // host memory: system-scope stores; the host waits for seq, so it
+                       // can return while the emitting pass still runs
             __hip_atomic_store(&report->tris, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             __hip_atomic_store(&report->blocks, (unsigned long long)blocks, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&report->seq, (unsigned long long)seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }

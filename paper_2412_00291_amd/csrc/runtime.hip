@@ -26,7 +26,8 @@ struct map_s {
     Counters *h_ctr = nullptr;  // pinned mirror for read-back
     MeshReport *h_report = nullptr;  // host-mapped, written by the extraction's scan kernel
     MeshReport *d_report = nullptr;  // the same memory as seen by the device
-    hipEvent_t done = nullptr;       // recorded after an extraction, waited on by spinning
+    hipEvent_t done = nullptr;       // recorded after an extraction (error detection)
+    uint32_t n_extract = 0;          // extractions launched (the report's seq of the last one)
     hipStream_t last_stream = nullptr;
     bool has_scan = false;
     MeshScan scan{};        // extraction scratch, kMaxMeshGrid workgroups
@@ -73,13 +74,20 @@ static int fail(map_t *m, int code, const char *fmt, ...)
                         __LINE__);                                                                \
     } while (0)
 
-// Wait for an event by polling: a blocking wait can sleep, and waking costs more than
-// the frame's last kernels take.
-static hipError_t spin_wait(hipEvent_t e)
+// Wait for an extraction's report (written by the scan that follows the counting pass,
+// before the emitting pass runs) by polling host-mapped memory, so the call returns while
+// the triangles are still being emitted on the stream.  Every 64 polls the event recorded
+// after the extraction is queried: a device error ends the wait, and so does the
+// extraction's completion without the expected report (hipErrorUnknown).
+static hipError_t wait_report(const MeshReport *r, uint32_t seq, hipEvent_t done)
 {
-    for (;;) {
-        const hipError_t q = hipEventQuery(e);
-        if (q != hipErrorNotReady) return q;
+    for (unsigned i = 1;; ++i) {
+        if (__atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
+        if (i % 64) continue;
+        const hipError_t q = hipEventQuery(done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return q;
+        return __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == seq ? hipSuccess : hipErrorUnknown;
     }
 }
 
@@ -255,6 +263,7 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&m->scan.wg_off, kMaxMeshGrid * sizeof(long long)));
     CREATE_TRY(hipHostMalloc((void **)&m->h_ctr, sizeof(Counters), hipHostMallocDefault));
     CREATE_TRY(hipHostMalloc((void **)&m->h_report, sizeof(MeshReport), hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset(m->h_report, 0, sizeof(MeshReport));
     CREATE_TRY(hipHostGetDevicePointer((void **)&m->d_report, m->h_report, 0));
     CREATE_TRY(hipEventCreateWithFlags(&m->done, hipEventDisableTiming));
     CREATE_TRY(hipMemsetAsync(v.dw, 0, nb * kBlockVoxels * sizeof(float2), s));
@@ -485,8 +494,13 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
         return e != hipSuccess ? e : launch_mesh_finish(m->v, mode, out, m->scan, m->d_report, m->sched[2], grid, s);
     }));
     HIP_TRY(m, hipEventRecord(m->done, s));
-    HIP_TRY(m, spin_wait(m->done));
     m->last_stream = s;
+    const uint32_t seq = ++m->n_extract;
+    const hipError_t we = wait_report(m->h_report, seq, m->done);
+    if (we != hipSuccess) {
+        m->n_extract = (uint32_t)__atomic_load_n(&m->h_report->seq, __ATOMIC_ACQUIRE);
+        return fail(m, MAP_ERR_DEVICE, "extract_mesh: %s", hipGetErrorString(we));
+    }
     const int64_t n = (int64_t)__atomic_load_n(&m->h_report->tris, __ATOMIC_ACQUIRE);
     *n_tris = n;
     if (n > cap_tris)
@@ -744,6 +758,7 @@ extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out
                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
               hipHostGetDevicePointer((void **)&b->d_reports, b->h_reports, 0) == hipSuccess &&
               hipEventCreateWithFlags(&b->done, hipEventDisableTiming) == hipSuccess;
+    if (ok) std::memset(b->h_reports, 0, kMaxBatchMaps * sizeof(MeshReport));
     if (ok) {
         std::memset(b->h_ctl, 0, sizeof(BatchCtl));
         ok = hipMemcpy(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice) == hipSuccess &&
@@ -839,6 +854,9 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         b->err = std::string(what) + ": " + hipGetErrorString(e);
         return MAP_ERR_DEVICE;
     };
+    // Report slots follow item order, so clear their sequence numbers (no device write to
+    // them is pending: the previous step returned after all of its reports).
+    for (int i = 0; i < n; ++i) __atomic_store_n(&b->h_reports[i].seq, 0ull, __ATOMIC_RELEASE);
     hipError_t e = hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(BatchMap), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_b(e, "descriptor upload");
     if (b->use_graph && s != nullptr) {  // the legacy default stream cannot be captured
@@ -867,8 +885,18 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
     }
     e = hipEventRecord(b->done, s);
     if (e != hipSuccess) return fail_b(e, "step event");
-    e = spin_wait(b->done);
-    if (e != hipSuccess) return fail_b(e, "step");
+    for (int i = 0; i < n; ++i) {
+        map_t *m = b->maps[items[i].map_index];
+        const uint32_t seq = ++m->n_extract;
+        e = wait_report(&b->h_reports[i], seq, b->done);
+        if (e != hipSuccess) {
+            for (int j = i; j < n; ++j) {
+                map_t *mj = b->maps[items[j].map_index];
+                mj->n_extract = (uint32_t)__atomic_load_n(&b->h_reports[j].seq, __ATOMIC_ACQUIRE);
+            }
+            return fail_b(e, "step");
+        }
+    }
     int rc = MAP_OK;
     for (int i = 0; i < n; ++i) {
         map_t *m = b->maps[items[i].map_index];
