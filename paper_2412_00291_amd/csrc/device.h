@@ -532,6 +532,7 @@ __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const
                                                          const Pose &T, const float *__restrict__ range, int e,
                                                          unsigned long long key, int slot, int rank)
 {
+    static_assert(kWidth % 64 == 0, "a wavefront covers whole z slices");
     constexpr int kV = kBlockVoxels / kWidth;
     const int3 bc = unpack_key(key);
     float2 *dwb = m.dw + (size_t)slot * kBlockVoxels;
@@ -553,8 +554,14 @@ __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const
             dwb[li] = v[it];
             upd++;
         }
+        // the wavefront holds z slice li / 64: its band bits and its voxel masks
         const unsigned long long bits = __ballot(band);
-        if ((threadIdx.x & 63) == 0) f.band[(size_t)e * 8 + (li >> 6)] = bits;
+        const unsigned long long sg = __ballot(v[it].x < 0.0f), ob = __ballot(v[it].y > 0.0f);
+        if ((threadIdx.x & 63) == 0) {
+            f.band[(size_t)e * 8 + (li >> 6)] = bits;
+            m.vmask[(size_t)slot * 16 + (li >> 6)] = sg;
+            m.vmask[(size_t)slot * 16 + 8 + (li >> 6)] = ob;
+        }
     }
     return upd;
 }

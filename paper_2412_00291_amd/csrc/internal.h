@@ -65,6 +65,8 @@ struct MapView {
     uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
     uint16_t *mesh_cnt;       // [max_blocks] triangles of a block in the current extraction
     int32_t *mesh_nbr;        // [max_blocks][8] slots of b + e, e in {0,1}^3 (-1: absent), same
+    unsigned long long *vmask;  // [max_blocks][16] per z slice: sign bits (D < 0), then observed
+                                // bits (W > 0), bit y * 8 + x; kept by the TSDF pass
     Counters *ctr;
     SyncState *sync;
     uint32_t hmask;

@@ -254,7 +254,7 @@ __device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_
 // wavefront schedule); per-map totals are summed in LDS.
 __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, BatchCtl *ctl, MeshScan scan, int n)
 {
-    __shared__ MeshSmem<1, HaloCode> S;
+    __shared__ MeshSmem<1, HaloMask> S;
     __shared__ int s_pre[kMaxBatchMaps + 1];
     __shared__ uint32_t s_epoch[kMaxBatchMaps];
     __shared__ unsigned long long s_tris[kMaxBatchMaps];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
             batch_lookup(maps, s_pre, n, S, j0, nb, false);
             for (int j = wave; j < nb; j += kThreads / 64) {
                 const int mi = S.mis[j];
-                mesh_stage_rows<false>(maps[mi].v, S.nbs[j], S.h[wave], lane);
+                mesh_stage_masks(maps[mi].v, S.nbs[j], S.h[wave], lane);
                 const unsigned long long t =
                     wave_sum_u64((unsigned long long)mesh_classify_rows(S.h[wave], S.ntri, lane, nullptr, &counts));
                 wave_lds_sync();
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
                 const BatchMap &B = maps[mr];
                 int mine = 0;
                 if (has) {
-                    mesh_stage_rows<true>(B.v, S.nbs[j], S.h[wave], lane);
+                    mesh_stage_rows(B.v, S.nbs[j], S.h[wave], lane);
                     if (lane == 0) S.rbc[wave] = S.bcs[j];
                     mine = mesh_classify_rows(S.h[wave], S.ntri, lane, S.ccase[wave], &counts);
                 }

@@ -6,14 +6,13 @@
 
 namespace mc {
 
-template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, MeshScan scan)
 {
-    __shared__ MeshSmem<kSched, HaloCode> S;
+    __shared__ MeshSmem<1, HaloMask> S;
     const Counters *c = m.ctr;
     long long tris;
     int blocks;
-    mesh_count_wg<kSched>(m, mode != 0, c->dirty_epoch, c->pool_used, S, &tris, &blocks);
+    mesh_count_wg(m, mode != 0, c->dirty_epoch, c->pool_used, S, &tris, &blocks);
     if (threadIdx.x == 0) {
         scan.wg_tris[blockIdx.x] = tris;
         scan.wg_blocks[blockIdx.x] = blocks;
@@ -40,7 +39,7 @@ MeshGrid mesh_grid(int schedule)
     static MeshGrid cached[2] = {{0, 0}, {0, 0}};
     const int k = schedule != 0;
     if (!cached[k].emit)
-        cached[k] = k == 0 ? resident_grids(k_mesh_count<0>, k_mesh_emit<0>) : resident_grids(k_mesh_count<1>, k_mesh_emit<1>);
+        cached[k] = k == 0 ? resident_grids(k_mesh_count, k_mesh_emit<0>) : resident_grids(k_mesh_count, k_mesh_emit<1>);
     return cached[k];
 }
 
@@ -49,8 +48,7 @@ hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, i
 {
     if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
         return hipErrorInvalidValue;
-    if (schedule == 0) hipLaunchKernelGGL(k_mesh_count<0>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
-    else hipLaunchKernelGGL(k_mesh_count<1>, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
+    hipLaunchKernelGGL(k_mesh_count, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
     return hipGetLastError();
 }
 

@@ -11,14 +11,15 @@
 
 namespace mc {
 
-// A staged halo: per voxel a code byte (bit 0: D < 0, bit 1: W > 0) for the cube cases;
-// the emitting pass also keeps D and the fused label for the vertices.
-// The wavefront schedule stages the halo by x-rows instead: rows[y + 9 z] holds the sign
-// bits (bits 0-8, D < 0) and observed bits (bits 16-24, W > 0) of the 9 voxels of row
-// (y, z), so a cube's case comes from four row words.
+// A staged halo.  rows[y + 9 z] holds the sign bits (bits 0-8, D < 0) and observed bits
+// (bits 16-24, W > 0) of the 9 voxels of x-row (y, z), so a cube's case comes from four
+// row words.  The counting pass builds the rows from the voxel masks of the eight blocks
+// (kept by the TSDF pass, 128 bytes per block); the emitting pass stages D and the fused
+// label for the vertices, and per voxel a code byte (bit 0: D < 0, bit 1: W > 0) for the
+// workgroup schedule's cube cases.
 constexpr int kHaloRows = kHalo * kHalo;
-struct HaloCode {
-    uint8_t code[kHaloVoxels];
+struct HaloMask {
+    unsigned long long mk[8][16];  // voxel masks of the blocks b + e (zero when absent)
     uint32_t rows[kHaloRows];
 };
 struct HaloFull {
@@ -111,18 +112,6 @@ __device__ __forceinline__ uint8_t voxel_code(float2 v)
 // Stage the halo of the block whose neighbour slots are nb[8] (absent blocks are
 // unobserved); rank is the lane's index among the worker's kWidth.
 template <int kSched>
-__device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, HaloCode &S, int rank)
-{
-    constexpr int kWidth = kSched == 0 ? kThreads : 64;
-    for (int h = rank; h < kHaloVoxels; h += kWidth) {
-        const int hx = h % kHalo, hy = (h / kHalo) % kHalo, hz = h / (kHalo * kHalo);
-        const int s = nb[(hx >> 3) | ((hy >> 3) << 1) | ((hz >> 3) << 2)];
-        S.code[h] = s >= 0 ? voxel_code(m.dw[(size_t)s * kBlockVoxels + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7)]) : 0;
-    }
-    worker_sync<kSched>();
-}
-
-template <int kSched>
 __device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, HaloFull &S, int rank)
 {
     constexpr int kWidth = kSched == 0 ? kThreads : 64;
@@ -150,10 +139,9 @@ __device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, Halo
 // observed (W > 0).
 // Stage a halo by rows (one wavefront): lane l takes rows l and l + 64.  A row's 8
 // voxels of one block are 64 contiguous bytes (four 16-byte loads), the 9th is the first
-// voxel of the +x neighbour's row.  With kFull the row's D values and fused labels are
-// staged too (halo index x + 9 row).
-template <bool kFull, class Halo>
-__device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb, Halo &S, int lane)
+// voxel of the +x neighbour's row.  The row's D values and fused labels are staged too
+// (halo index x + 9 row).
+__device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb, HaloFull &S, int lane)
 {
     for (int r = lane; r < kHaloRows; r += 64) {
         const int y = r % kHalo, z = r / kHalo;
@@ -173,9 +161,8 @@ __device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb,
             float4 q[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) q[i] = p[i];
-            unsigned long long f8 = 0;
-            if constexpr (kFull)
-                f8 = *reinterpret_cast<const unsigned long long *>(m.fused + (size_t)s0 * kBlockVoxels + off);
+            const unsigned long long f8 =
+                *reinterpret_cast<const unsigned long long *>(m.fused + (size_t)s0 * kBlockVoxels + off);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float D0 = q[i].x, W0 = q[i].y, D1 = q[i].z, W1 = q[i].w;
@@ -193,16 +180,36 @@ __device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb,
             sign |= (v.x < 0.0f ? 1u : 0u) << 8;
             obs |= (v.y > 0.0f ? 1u : 0u) << 8;
             d[8] = v.x;
-            if constexpr (kFull) fu[8] = m.fused[vi];
+            fu[8] = m.fused[vi];
         }
         S.rows[r] = sign | (obs << 16);
-        if constexpr (kFull) {
 #pragma unroll
-            for (int x = 0; x < kHalo; ++x) {
-                S.d[kHalo * r + x] = d[x];
-                S.fused[kHalo * r + x] = fu[x];
-            }
+        for (int x = 0; x < kHalo; ++x) {
+            S.d[kHalo * r + x] = d[x];
+            S.fused[kHalo * r + x] = fu[x];
         }
+    }
+    wave_lds_sync();
+}
+
+// Stage a block's halo rows from the voxel masks of its eight blocks (one wavefront):
+// lane l copies 16 bytes of block l / 8's masks into LDS, then builds rows l and l + 64.
+__device__ __forceinline__ void mesh_stage_masks(const MapView &m, const int *nb, HaloMask &S, int lane)
+{
+    const int jj = lane >> 3, q = lane & 7;
+    const int s = nb[jj];
+    ulonglong2 v = make_ulonglong2(0ull, 0ull);
+    if (s >= 0) v = reinterpret_cast<const ulonglong2 *>(m.vmask + (size_t)s * 16)[q];
+    reinterpret_cast<ulonglong2 *>(S.mk[jj])[q] = v;
+    wave_lds_sync();
+    for (int r = lane; r < kHaloRows; r += 64) {
+        const int y = r % kHalo, z = r / kHalo;
+        const int j0 = ((y >> 3) << 1) | ((z >> 3) << 2);
+        const int sl = z & 7, sh = 8 * (y & 7);
+        const uint32_t sign = (uint32_t)((S.mk[j0][sl] >> sh) & 0xFFu) | (uint32_t)((S.mk[j0 | 1][sl] >> sh) & 1u) << 8;
+        const uint32_t obs =
+            (uint32_t)((S.mk[j0][8 + sl] >> sh) & 0xFFu) | (uint32_t)((S.mk[j0 | 1][8 + sl] >> sh) & 1u) << 8;
+        S.rows[r] = sign | (obs << 16);
     }
     wave_lds_sync();
 }
@@ -407,10 +414,10 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
     return n;
 }
 
-// Counting pass of one workgroup: triangles and blocks over its candidates.
-template <int kSched>
+// Counting pass of one workgroup: triangles and blocks over its candidates, one
+// wavefront per block (halo rows from the voxel masks).
 __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32_t epoch, int nslots,
-                                              MeshSmem<kSched, HaloCode> &S, long long *tris, int *blocks)
+                                              MeshSmem<1, HaloMask> &S, long long *tris, int *blocks)
 {
     mesh_tables(S, false);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -423,41 +430,22 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
             mesh_batch_lookup(m, S, j0, nb, false);
-            if (kSched == 0) {
-                for (int j = 0; j < nb; ++j) {
-                    mesh_stage<0>(m, S.nbs[j], S.h[0], threadIdx.x);
-                    const unsigned long long t =
-                        wave_sum_u64((unsigned long long)mesh_classify<0>(S.h[0], S.ntri, threadIdx.x, nullptr, &counts));
-                    if (lane == 0) S.rcnt[wave] = (long long)t;
-                    __syncthreads();
-                    if (threadIdx.x == 0) {
-                        long long tot = 0;
-                        for (int w = 0; w < kThreads / 64; ++w) tot += S.rcnt[w];
-                        m.mesh_cnt[S.nbs[j][0]] = (uint16_t)tot;
-                        my_tris += tot;
-                    }
-                    __syncthreads();  // the halo and counts are rewritten by the next block
+            for (int j = wave; j < nb; j += kThreads / 64) {
+                mesh_stage_masks(m, S.nbs[j], S.h[wave], lane);
+                const unsigned long long t =
+                    wave_sum_u64((unsigned long long)mesh_classify_rows(S.h[wave], S.ntri, lane, nullptr, &counts));
+                wave_lds_sync();
+                if (lane == 0) {
+                    m.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
+                    my_tris += (long long)t;
+                    my_blocks += 1;
                 }
-                my_blocks += nb;
-            } else {
-                for (int j = wave; j < nb; j += kThreads / 64) {
-                    mesh_stage_rows<false>(m, S.nbs[j], S.h[wave], lane);
-                    const unsigned long long t =
-                        wave_sum_u64((unsigned long long)mesh_classify_rows(S.h[wave], S.ntri, lane, nullptr, &counts));
-                    wave_lds_sync();
-                    if (lane == 0) {
-                        m.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
-                        my_tris += (long long)t;
-                        my_blocks += 1;
-                    }
-                }
-                __syncthreads();  // the batch's lookups are rewritten by the next batch
             }
+            __syncthreads();  // the batch's lookups are rewritten by the next batch
         }
         __syncthreads();  // the list is rewritten by the next iteration
     }
-    // workgroup totals (kept on thread 0 of a workgroup worker, lane 0 of a wave worker)
-    if (kSched == 0 && threadIdx.x != 0) my_blocks = 0;
+    // workgroup totals (kept on lane 0 of each wavefront)
     unsigned long long t = wave_sum_u64((unsigned long long)my_tris);
     unsigned long long b = wave_sum_u64((unsigned long long)my_blocks);
     if (lane == 0) {
@@ -506,7 +494,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
                     if (rank == 0) S.rbc[0] = S.bcs[j];
                     mine = mesh_classify<0>(S.h[0], S.ntri, rank, S.ccase[0], &counts);
                 } else if (has) {
-                    mesh_stage_rows<true>(m, S.nbs[j], S.h[worker], lane);
+                    mesh_stage_rows(m, S.nbs[j], S.h[worker], lane);
                     if (lane == 0) S.rbc[worker] = S.bcs[j];
                     mine = mesh_classify_rows(S.h[worker], S.ntri, lane, S.ccase[worker], &counts);
                 }
