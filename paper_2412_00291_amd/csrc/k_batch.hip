@@ -265,11 +265,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_count(BatchMap *maps, B
         s_blocks[m] = 0;
     }
     load_prefix(s_pre, ctl->pre_p, n);
-    mesh_tables(S, false);
+    const TableRegs tab = mesh_tables_load<false>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned counts;
     for (int it = 0;; ++it) {
         const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, false, S);
+        if (it == 0) mesh_tables_store<false>(S, tab);
         if (cnt < 0) break;
         for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
             const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;
@@ -320,11 +321,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
         s_next[m] = scan.wg_off[(size_t)blockIdx.x * n + m];
     }
     load_prefix(s_pre, ctl->pre_p, n);
-    mesh_tables(S, true);
+    const TableRegs tab = mesh_tables_load<true>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned counts = 0;
     for (int it = 0;; ++it) {
         const int cnt = batch_candidates(maps, s_pre, s_epoch, n, it, true, S);
+        if (it == 0) mesh_tables_store<true>(S, tab);
         if (cnt < 0) break;
         for (int j0 = 0; j0 < cnt; j0 += kMeshBatch) {
             const int nb = cnt - j0 < kMeshBatch ? cnt - j0 : kMeshBatch;

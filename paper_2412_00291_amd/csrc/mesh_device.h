@@ -54,19 +54,42 @@ struct __align__(16) MeshSmem {
     long long rcnt[kThreads / 64];
 };
 
-// Copy the case tables into the workgroup's LDS with dword loads (every thread).  No
-// barrier of its own: the candidate scan that follows has barriers before any cube is
-// classified, and the table loads overlap its loads.
-template <class Smem>
-__device__ __forceinline__ void mesh_tables(Smem &S, bool with_tris)
+// The case tables reach the workgroup's LDS in two steps: every thread loads its dwords
+// (t, t + kThreads, ...) into registers before the first candidate scan, so that the two
+// loads overlap, and stores them after it; the scan's and the lookup's barriers order the
+// stores before any cube is classified.  The counting pass needs only the triangle counts.
+constexpr int kTabDwords = (256 + 256 * kTriRow) / 4;
+constexpr int kTabPer = (kTabDwords + kThreads - 1) / kThreads;
+struct TableRegs {
+    uint32_t v[kTabPer];
+};
+
+template <bool kTris>
+__device__ __forceinline__ TableRegs mesh_tables_load()
 {
     const uint32_t *ntri = reinterpret_cast<const uint32_t *>(MC_NTRI);
+    const uint32_t *tris = reinterpret_cast<const uint32_t *>(MC_TRIS);
+    TableRegs r;
+#pragma unroll
+    for (int k = 0; k < kTabPer; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        r.v[k] = 0;
+        if (i < 64) r.v[k] = ntri[i];
+        else if (kTris && i < kTabDwords) r.v[k] = tris[i - 64];
+    }
+    return r;
+}
+
+template <bool kTris, class Smem>
+__device__ __forceinline__ void mesh_tables_store(Smem &S, const TableRegs &r)
+{
     uint32_t *ntri_s = reinterpret_cast<uint32_t *>(S.ntri);
-    for (int i = threadIdx.x; i < 256 / 4; i += kThreads) ntri_s[i] = ntri[i];
-    if (with_tris) {
-        const uint32_t *tris = reinterpret_cast<const uint32_t *>(MC_TRIS);
-        uint32_t *tris_s = reinterpret_cast<uint32_t *>(S.tris);
-        for (int i = threadIdx.x; i < 256 * kTriRow / 4; i += kThreads) tris_s[i] = tris[i];
+    uint32_t *tris_s = reinterpret_cast<uint32_t *>(S.tris);
+#pragma unroll
+    for (int k = 0; k < kTabPer; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        if (i < 64) ntri_s[i] = r.v[k];
+        else if (kTris && i < kTabDwords) tris_s[i - 64] = r.v[k];
     }
 }
 
@@ -419,13 +442,14 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
 __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32_t epoch, int nslots,
                                               MeshSmem<1, HaloMask> &S, long long *tris, int *blocks)
 {
-    mesh_tables(S, false);
+    const TableRegs tab = mesh_tables_load<false>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     long long my_tris = 0;
     int my_blocks = 0;
     unsigned counts;
     for (int it = 0;; ++it) {
         const int n = mesh_candidates(m, all, epoch, nslots, it, false, S);
+        if (it == 0) mesh_tables_store<false>(S, tab);
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
@@ -473,7 +497,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
                                              const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st)
 {
     constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
-    mesh_tables(S, true);
+    const TableRegs tab = mesh_tables_load<true>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int worker = kSched == 0 ? 0 : wave;
@@ -481,6 +505,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
     long long carry = base;
     for (int it = 0;; ++it) {
         const int n = mesh_candidates(m, all, epoch, nslots, it, true, S);
+        if (it == 0) mesh_tables_store<true>(S, tab);
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;

@@ -429,7 +429,7 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] { return launch_alloc(m->v, m->f, m->lut, T, range_dev, s); }));
     const uint32_t fid = m->frame_id++;
     HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
-        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, 2048), s);
+        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, 1024), s);
     }));
     m->last_stream = s;
     m->has_scan = true;
