@@ -77,25 +77,98 @@ def algorithmic_bytes(kernel, s, rows, cols, cams):
     return 0
 
 
-def measured_traffic(kernel, sched):
-    """HBM bytes per launch of a kernel group from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel sources (or the schedules) differ from the
-    ones the counters were taken on."""
+TRAFFIC_JSON = os.path.join("profiles", "street_64x2048_traffic.json")
+GROUPS = {"alloc": ("k_alloc",), "tsdf": ("k_tsdf<",), "labels": ("k_labels<",),
+          "mesh": ("k_mesh_count", "k_mesh_scan", "k_mesh_emit<")}
+
+
+def sources_sha256(root):
+    """Hash of the kernel sources (csrc *.hip, *.h and the case-table generator)."""
     import hashlib
-    root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "street_64x2048_traffic.json")
-    try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
-        return None
     csrc = os.path.join(root, "paper_2412_00291_amd", "csrc")
     names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".h"))) + ["gen_mc_table.py"]
     h = hashlib.sha256()
     for n in sorted(os.path.join("paper_2412_00291_amd/csrc", x) for x in names):
         h.update(open(os.path.join(root, n), "rb").read())
-    if h.hexdigest() != rec.get("sources_sha256"):
+    return h.hexdigest()
+
+
+def _counter_rows(path):
+    import csv
+    rows = []
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].replace("void ", "").split("(")[0].replace("mc::", "")
+        rows.append((int(r["Dispatch_Id"]), name, float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def write_traffic(out_dir):
+    """Summarise the rocprofv3 FETCH_SIZE / WRITE_SIZE runs under out_dir (pmc_<C>/street_*
+    of `bench.py --steps K --warmup W --no-cpu-baseline --no-extensions`, cal_<C>/copy_* of
+    `bench.py --calibrate-copy`) into the HBM bytes per launch of each kernel group: the
+    last K dispatches of the instances of the schedules that run chose (its per-kernel
+    breakdown pass), each counter scaled by the copy calibration."""
+    import glob
+    bench = json.load(open(os.path.join(out_dir, "pmc_FETCH_SIZE.json")))
+    K = bench["steps"]
+    sch = bench["schedules"]
+    want = {"tsdf": f"k_tsdf<{sch['tsdf']}", "labels": f"k_labels<{sch['labels']}",
+            "mesh_emit": f"k_mesh_emit<{sch['mesh']}>"}
+    per = {}
+    factors = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = _counter_rows(glob.glob(os.path.join(out_dir, f"cal_{c}", "*counter_collection.csv"))[0])
+        copy_kib = max(v for _, n, v in cal if "copyBuffer" in n)
+        factors[c] = (256 << 10) / copy_kib  # a 256 MiB copy reads and writes 262144 KiB
+        rows = _counter_rows(glob.glob(os.path.join(out_dir, f"pmc_{c}", "*counter_collection.csv"))[0])
+        by = {}
+        for _, n, v in rows:
+            by.setdefault(n, []).append(v)
+        per[c] = by
+    out = {}
+    kernels = {}
+    for g, prefixes in GROUPS.items():
+        total = 0.0
+        for n in per["FETCH_SIZE"]:
+            if not any(n.startswith(p) for p in prefixes):
+                continue
+            if n.startswith("k_tsdf<") and not n.startswith(want["tsdf"]):
+                continue
+            if n.startswith("k_labels<") and not n.startswith(want["labels"]):
+                continue
+            if n.startswith("k_mesh_emit<") and n != want["mesh_emit"]:
+                continue
+            f = per["FETCH_SIZE"][n][-K:]
+            w = per["WRITE_SIZE"].get(n, [0.0])[-K:]
+            fb = 1024 * factors["FETCH_SIZE"] * sum(f) / len(f)
+            wb = 1024 * factors["WRITE_SIZE"] * sum(w) / len(w)
+            kernels[n] = {"fetch_kib": sum(f) / len(f), "write_kib": sum(w) / len(w), "bytes": fb + wb}
+            total += fb + wb
+        out[g] = total
+    rec = {"workload": "street-64x2048-v0.1", "sources_sha256": sources_sha256(ROOT),
+           "fetch_factor": factors["FETCH_SIZE"], "write_factor": factors["WRITE_SIZE"],
+           "bytes_per_launch": out, "kernels": kernels, "dispatches_per_kernel": K,
+           "schedules": {k: sch[k] for k in ("tsdf", "labels", "mesh")},
+           "note": "FETCH_SIZE and WRITE_SIZE KiB per dispatch x the copy-calibrated factors, "
+                   "summed over the group's kernels (street_64x2048_traffic.md gives the commands)"}
+    path = os.path.join(ROOT, TRAFFIC_JSON)
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def measured_traffic(kernel, sched):
+    """HBM bytes per launch of a kernel group from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel sources (or the group's schedule) differ
+    from the ones the counters were taken on."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, TRAFFIC_JSON)))
+    except (OSError, ValueError):
         return None
-    if any(rec.get("schedules", {}).get(k) != v for k, v in sched.items()):
+    if sources_sha256(ROOT) != rec.get("sources_sha256"):
+        return None
+    if kernel in sched and rec.get("schedules", {}).get(kernel) != sched[kernel]:
         return None
     return rec.get("bytes_per_launch", {}).get(kernel)
 
@@ -341,7 +414,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--write-traffic", metavar="DIR",
+                    help="summarise rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into " + TRAFFIC_JSON)
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
               "(maps shard by block ownership, see the design notes)", file=sys.stderr)
