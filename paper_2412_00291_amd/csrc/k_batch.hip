@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_mesh_emit(BatchMap *maps, Ba
                     rtot += c;
                 }
                 const long long r0 = s_next[mr];
-                mesh_round_out<1>(B.v, S, st, has, wave, lane, counts, woff + incl - mine, mine, rtot, r0, B.out);
+                mesh_round_out<1>(B.v, S, st, has, counts, woff + incl - mine, rtot, r0, B.out);
                 __syncthreads();  // every thread has read s_next[mr] and the round's counts
                 if (threadIdx.x == 0) s_next[mr] = r0 + rtot;
                 __syncthreads();

@@ -291,45 +291,27 @@ __device__ __forceinline__ int mesh_classify(const Halo &S, const uint8_t *ntri,
     return mine;
 }
 
-// Triangles are emitted a window of kStageTris at a time: every lane records a 2-byte
-// descriptor (worker, cube, triangle of the cube) per triangle of its cubes in the
-// window, then each thread builds whole triangles (one per thread, consecutive threads
-// consecutive triangles) into an LDS stage, which the workgroup copies out with
-// consecutive-address stores.
+// Triangles are emitted a window of kStageTris at a time: each thread finds the cube and
+// triangle of one window index from the round's per-lane start indices and packed cube
+// counts (a binary search over the workgroup's lanes, then a walk over the lane's cubes),
+// builds that whole triangle into an LDS stage, and the workgroup copies the window out
+// with consecutive-address stores.
 constexpr int kStageTris = 256;
 struct MeshStage {
     float pos[kStageTris * 9];
     uint8_t lab[kStageTris * 3];
-    uint16_t desc[kStageTris];  // worker << 12 | cube << 3 | triangle
+    int lo[kThreads];        // first round index of each lane's triangles
+    unsigned cnt[kThreads];  // each lane's cube triangle counts, 4 bits per cube
 };
 
-// Descriptors of the lane's triangles whose index within the round lies in
-// [w0, w0 + kStageTris); lo is the lane's first index within the round.
-template <int kSched>
-__device__ __forceinline__ void mesh_desc(int worker, int rank, unsigned counts, int lo, int mine, int w0,
-                                          MeshStage &st)
-{
-    constexpr int kWidth = kSched == 0 ? kThreads : 64;
-    constexpr int kCubes = kBlockVoxels / kWidth;
-    if (mine == 0 || lo >= w0 + kStageTris || lo + mine <= w0) return;
-    int r = lo;
-#pragma unroll
-    for (int it = 0; it < kCubes; ++it) {
-        const int nt = (counts >> (4 * it)) & 15;
-        const int cube = kSched == 0 ? it * kWidth + rank : it + 8 * rank;  // the rows' cube order
-        for (int q = 0; q < nt; ++q, ++r)
-            if (r >= w0 && r < w0 + kStageTris) st.desc[r - w0] = (uint16_t)((worker << 12) | (cube << 3) | q);
-    }
-}
-
-// Build staged triangle i of the window from its descriptor; g is its output index.
+// Build staged triangle i of the window from its descriptor d (worker << 12 | cube << 3 |
+// triangle of the cube); g is its output index.
 // Edge keys, when asked for, go straight to global memory (indices at or past out.cap
 // are dropped: the extraction then reports the size it needs).
 template <class Smem>
-__device__ __forceinline__ void mesh_tri(const MapView &m, const Smem &S, MeshStage &st, int i, long long g,
+__device__ __forceinline__ void mesh_tri(const MapView &m, const Smem &S, MeshStage &st, int i, int d, long long g,
                                          const MeshOut &out)
 {
-    const int d = st.desc[i];
     const int wk = d >> 12, cube = (d >> 3) & 511, q = d & 7;
     const HaloFull &H = S.h[wk];
     const int4 bc = S.rbc[wk];
@@ -374,17 +356,43 @@ __device__ __forceinline__ void mesh_flush(const MeshStage &st, int n, long long
 
 // One round's output (its blocks' triangles are contiguous from output index r0): the
 // lane's triangles are [lo, lo + mine) within the round of rtot; every thread of the
-// workgroup calls it.
+// workgroup calls it.  Lane start indices never decrease with the thread index, so the
+// last lane whose start is at most i is the one that holds round index i.
 template <int kSched, class Smem>
-__device__ __forceinline__ void mesh_round_out(const MapView &m, const Smem &S, MeshStage &st, bool has, int worker,
-                                               int rank, unsigned counts, int lo, int mine, int rtot, long long r0,
-                                               const MeshOut &out)
+__device__ __forceinline__ void mesh_round_out(const MapView &m, const Smem &S, MeshStage &st, bool has,
+                                               unsigned counts, int lo, int rtot, long long r0, const MeshOut &out)
 {
+    constexpr int kWidth = kSched == 0 ? kThreads : 64;
+    constexpr int kCubes = kBlockVoxels / kWidth;
+    st.lo[threadIdx.x] = lo;
+    st.cnt[threadIdx.x] = has ? counts : 0u;
+    __syncthreads();
     for (int w0 = 0; w0 < rtot; w0 += kStageTris) {
         const int nw = rtot - w0 < kStageTris ? rtot - w0 : kStageTris;
-        if (has) mesh_desc<kSched>(worker, rank, counts, lo, mine, w0, st);
-        __syncthreads();
-        for (int i = threadIdx.x; i < nw; i += kThreads) mesh_tri(m, S, st, i, r0 + w0 + i, out);
+        const int i = threadIdx.x;
+        if (i < nw) {
+            const int g = w0 + i;
+            int T = 0;
+#pragma unroll
+            for (int step = kThreads / 2; step > 0; step >>= 1)
+                if (st.lo[T + step] <= g) T += step;
+            const unsigned c = st.cnt[T];
+            int local = g - st.lo[T], it_hit = 0, q = 0;
+            bool found = false;
+#pragma unroll
+            for (int it = 0; it < kCubes; ++it) {
+                const int nt = (int)((c >> (4 * it)) & 15u);
+                if (!found && local < nt) {
+                    found = true;
+                    it_hit = it;
+                    q = local;
+                }
+                local -= found ? 0 : nt;
+            }
+            const int worker = kSched == 0 ? 0 : T >> 6, rank = kSched == 0 ? T : T & 63;
+            const int cube = kSched == 0 ? it_hit * kWidth + rank : it_hit + 8 * rank;  // the rows' cube order
+            mesh_tri(m, S, st, i, (worker << 12) | (cube << 3) | q, r0 + g, out);
+        }
         __syncthreads();
         mesh_flush(st, nw, r0 + w0, out);
         __syncthreads();
@@ -533,7 +541,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
                     woff += w < wave ? c : 0;
                     rtot += c;
                 }
-                mesh_round_out<kSched>(m, S, st, has, worker, rank, counts, woff + incl - mine, mine, rtot, carry, out);
+                mesh_round_out<kSched>(m, S, st, has, counts, woff + incl - mine, rtot, carry, out);
                 carry += rtot;
                 __syncthreads();  // the round's counts are rewritten by the next round
             }
