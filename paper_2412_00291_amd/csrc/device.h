@@ -612,6 +612,22 @@ __device__ __forceinline__ void close_frame_wave(const MapView &m, const FrameSt
 // the count), and writes each changed count once.
 // Band voxels of a touched block, compacted: load the block's 8 band words and their
 // prefix popcounts; band_select gives the voxel of the t-th set bit.
+// Voxel index of the r-th set bit (r < popcount) of band word k.
+__device__ __forceinline__ int band_bit(unsigned long long x, int k, int r)
+{
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const int c = __popcll(x & ((1ull << width) - 1ull));
+        if (r >= c) {
+            r -= c;
+            x >>= width;
+            pos += width;
+        }
+    }
+    return 64 * k + pos;
+}
+
 struct BandWords {
     unsigned long long w[8];
     int pre[9];
@@ -641,17 +657,35 @@ __device__ __forceinline__ int band_select(const BandWords &b, int t)
         x = k == j ? b.w[j] : x;
         pk = k == j ? b.pre[j] : pk;
     }
-    int r = t - pk, pos = 0;
+    return band_bit(x, k, t - pk);
+}
+
+// A workgroup's band voxels over a group of up to kLabGroup touched entries, as one flat
+// list: the entries' band words, slots and keys in LDS, each entry's word prefix, and the
+// entries' voxel prefix, so the workgroup's threads take consecutive voxels of the whole
+// group in one pass instead of one entry after another.
+constexpr int kLabGroup = 8;
+struct LabelGroup {
+    unsigned long long w[kLabGroup][8];
+    unsigned long long key[kLabGroup];
+    int slot[kLabGroup];
+    int pre[kLabGroup][9];
+};
+
+// Voxel t (< the group's total) of the group: entry j, voxel index li.
+__device__ __forceinline__ void label_group_voxel(const LabelGroup &g, const int *epre, int t, int &j, int &li)
+{
+    j = 0;
 #pragma unroll
-    for (int width = 32; width >= 1; width >>= 1) {  // r-th set bit of x
-        const int c = __popcll(x & ((1ull << width) - 1ull));
-        if (r >= c) {
-            r -= c;
-            x >>= width;
-            pos += width;
-        }
-    }
-    return 64 * k + pos;
+    for (int i = 1; i < kLabGroup; ++i) j += epre[i] <= t ? 1 : 0;
+    int base = 0;  // selects, not indexing: epre stays in registers
+#pragma unroll
+    for (int i = 1; i < kLabGroup; ++i) base = j == i ? epre[i] : base;
+    const int local = t - base;
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) k += g.pre[j][i] <= local ? 1 : 0;
+    li = band_bit(g.w[j][k], k, local - g.pre[j][k]);
 }
 
 constexpr int kCamChunk = 4;  // cameras whose votes one pass gathers (register budget)

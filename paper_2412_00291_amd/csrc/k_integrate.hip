@@ -172,18 +172,54 @@ template <int kSched>
 __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, CameraSet cs)
 {
     __shared__ unsigned long long s_sum[kThreads / 64];
+    __shared__ LabelGroup g;
     const int n = m.ctr->last_touched;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int kWidth = kSched == 0 ? kThreads : 64;
-    const int rank = kSched == 0 ? (int)threadIdx.x : lane;
-    const int first = kSched == 0 ? (int)blockIdx.x : (int)blockIdx.x * (kThreads / 64) + wave;
-    const int stride = kSched == 0 ? (int)gridDim.x : (int)gridDim.x * (kThreads / 64);
     unsigned long long my_votes = 0;
-    for (int e = first; e < n; e += stride) {
-        const int slot = f.tk_slot[e];
-        const int3 bc = unpack_key(f.tk_key[e]);
-        const BandWords b = band_words(f, e);
-        for (int t = rank; t < b.pre[8]; t += kWidth) my_votes += label_voxel(m, cs, slot, bc, band_select(b, t));
+    if (kSched == 0) {
+        // workgroup: its entries blockIdx + j G, kLabGroup at a time, voxels as one flat list
+        const int G = (int)gridDim.x;
+        for (int e0 = blockIdx.x; e0 < n; e0 += kLabGroup * G) {
+            if (threadIdx.x < kLabGroup * 8) {
+                const int j = threadIdx.x >> 3, k = threadIdx.x & 7, e = e0 + j * G;
+                g.w[j][k] = e < n ? f.band[(size_t)e * 8 + k] : 0ull;
+            }
+            if (threadIdx.x < kLabGroup) {
+                const int e = e0 + (int)threadIdx.x * G;
+                g.slot[threadIdx.x] = e < n ? f.tk_slot[e] : -1;
+                g.key[threadIdx.x] = e < n ? f.tk_key[e] : 0ull;
+            }
+            __syncthreads();
+            if (threadIdx.x < kLabGroup) {
+                int p = 0;
+                g.pre[threadIdx.x][0] = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    p += __popcll(g.w[threadIdx.x][k]);
+                    g.pre[threadIdx.x][k + 1] = p;
+                }
+            }
+            __syncthreads();
+            int epre[kLabGroup + 1];
+            epre[0] = 0;
+#pragma unroll
+            for (int j = 0; j < kLabGroup; ++j) epre[j + 1] = epre[j] + g.pre[j][8];
+            for (int t = threadIdx.x; t < epre[kLabGroup]; t += kThreads) {
+                int j, li;
+                label_group_voxel(g, epre, t, j, li);
+                my_votes += label_voxel(m, cs, g.slot[j], unpack_key(g.key[j]), li);
+            }
+            __syncthreads();  // the group's LDS is rewritten by the next group
+        }
+    } else {
+        // wavefront: one entry at a time
+        const int first = (int)blockIdx.x * (kThreads / 64) + wave, stride = (int)gridDim.x * (kThreads / 64);
+        for (int e = first; e < n; e += stride) {
+            const int slot = f.tk_slot[e];
+            const int3 bc = unpack_key(f.tk_key[e]);
+            const BandWords b = band_words(f, e);
+            for (int t = lane; t < b.pre[8]; t += 64) my_votes += label_voxel(m, cs, slot, bc, band_select(b, t));
+        }
     }
     unsigned long long w = wave_sum_u64(my_votes);
     if (lane == 0) s_sum[wave] = w;
