@@ -162,8 +162,9 @@ __device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, Halo
 // observed (W > 0).
 // Stage a halo by rows (one wavefront): lane l takes rows l and l + 64.  A row's 8
 // voxels of one block are 64 contiguous bytes (four 16-byte loads), the 9th is the first
-// voxel of the +x neighbour's row.  The row's D values and fused labels are staged too
-// (halo index x + 9 row).
+// voxel of the +x neighbour's row; both blocks' loads are issued before either is used,
+// so a row costs one memory round trip.  The row's D values and fused labels are staged
+// too (halo index x + 9 row).
 __device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb, HaloFull &S, int lane)
 {
     for (int r = lane; r < kHaloRows; r += 64) {
@@ -171,46 +172,43 @@ __device__ __forceinline__ void mesh_stage_rows(const MapView &m, const int *nb,
         const int jj = ((y >> 3) << 1) | ((z >> 3) << 2);
         const int s0 = nb[jj], s1 = nb[jj | 1];
         const int off = 8 * (y & 7) + 64 * (z & 7);
+        // branch-free loads (an absent block reads slot 0 and is then masked out), so the
+        // compiler issues all of them before the first use
+        const size_t v0 = (size_t)(s0 >= 0 ? s0 : 0) * kBlockVoxels + off;
+        const size_t v1 = (size_t)(s1 >= 0 ? s1 : 0) * kBlockVoxels + off;
+        float4 q[4];
+        const float4 *p = reinterpret_cast<const float4 *>(m.dw + v0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = p[i];
+        unsigned long long f8 = *reinterpret_cast<const unsigned long long *>(m.fused + v0);
+        float2 v9 = m.dw[v1];
+        uint8_t u9 = m.fused[v1];
+        if (s0 < 0) {  // absent: unobserved, fused 255
+#pragma unroll
+            for (int i = 0; i < 4; ++i) q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            f8 = ~0ull;
+        }
+        if (s1 < 0) {
+            v9 = make_float2(0.0f, 0.0f);
+            u9 = 255;
+        }
         uint32_t sign = 0, obs = 0;
-        float d[kHalo];
-        uint8_t fu[kHalo];
+        const int h = kHalo * r;
 #pragma unroll
-        for (int x = 0; x < kHalo; ++x) {
-            d[x] = 0.0f;
-            fu[x] = 255;
+        for (int i = 0; i < 4; ++i) {
+            const float D0 = q[i].x, W0 = q[i].y, D1 = q[i].z, W1 = q[i].w;
+            sign |= (D0 < 0.0f ? 1u : 0u) << (2 * i) | (D1 < 0.0f ? 1u : 0u) << (2 * i + 1);
+            obs |= (W0 > 0.0f ? 1u : 0u) << (2 * i) | (W1 > 0.0f ? 1u : 0u) << (2 * i + 1);
+            S.d[h + 2 * i] = D0;
+            S.d[h + 2 * i + 1] = D1;
         }
-        if (s0 >= 0) {
-            const float4 *p = reinterpret_cast<const float4 *>(m.dw + (size_t)s0 * kBlockVoxels + off);
-            float4 q[4];
+        sign |= (v9.x < 0.0f ? 1u : 0u) << 8;
+        obs |= (v9.y > 0.0f ? 1u : 0u) << 8;
+        S.d[h + 8] = v9.x;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) q[i] = p[i];
-            const unsigned long long f8 =
-                *reinterpret_cast<const unsigned long long *>(m.fused + (size_t)s0 * kBlockVoxels + off);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float D0 = q[i].x, W0 = q[i].y, D1 = q[i].z, W1 = q[i].w;
-                sign |= (D0 < 0.0f ? 1u : 0u) << (2 * i) | (D1 < 0.0f ? 1u : 0u) << (2 * i + 1);
-                obs |= (W0 > 0.0f ? 1u : 0u) << (2 * i) | (W1 > 0.0f ? 1u : 0u) << (2 * i + 1);
-                d[2 * i] = D0;
-                d[2 * i + 1] = D1;
-            }
-#pragma unroll
-            for (int x = 0; x < 8; ++x) fu[x] = (uint8_t)(f8 >> (8 * x));
-        }
-        if (s1 >= 0) {
-            const size_t vi = (size_t)s1 * kBlockVoxels + off;
-            const float2 v = m.dw[vi];
-            sign |= (v.x < 0.0f ? 1u : 0u) << 8;
-            obs |= (v.y > 0.0f ? 1u : 0u) << 8;
-            d[8] = v.x;
-            fu[8] = m.fused[vi];
-        }
+        for (int x = 0; x < 8; ++x) S.fused[h + x] = (uint8_t)(f8 >> (8 * x));
+        S.fused[h + 8] = u9;
         S.rows[r] = sign | (obs << 16);
-#pragma unroll
-        for (int x = 0; x < kHalo; ++x) {
-            S.d[kHalo * r + x] = d[x];
-            S.fused[kHalo * r + x] = fu[x];
-        }
     }
     wave_lds_sync();
 }
