@@ -223,10 +223,11 @@ __device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapVie
                                             const LidarLUT &L, const Pose &T, const float *__restrict__ range,
                                             int pix)
 {
-    float r = range[pix];
-    if (!valid_return(r, L.r_max)) return;
     const int k = pix / L.cols, c = pix - k * L.cols;
-    const float dx = L.ce[k] * L.cp[c], dy = L.ce[k] * L.sp[c], dz = L.se[k];
+    const float r = range[pix];
+    const float ce = L.ce[k], se = L.se[k], cp = L.cp[c], sp = L.sp[c];  // read with the return
+    if (!valid_return(r, L.r_max)) return;
+    const float dx = ce * cp, dy = ce * sp, dz = se;
     float s0 = r - m.tau;
     if (!(s0 > 0.0f)) s0 = 0.0f;
     const float s1 = r + m.tau;

@@ -195,14 +195,18 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
         // workgroup: its entries blockIdx + j G, kLabGroup at a time, voxels as one flat list
         const int G = (int)gridDim.x;
         for (int e0 = blockIdx.x; e0 < n; e0 += kLabGroup * G) {
-            if (threadIdx.x < kLabGroup * 8) {
-                const int j = threadIdx.x >> 3, k = threadIdx.x & 7, e = e0 + j * G;
-                g.w[j][k] = e < n ? f.band[(size_t)e * 8 + k] : 0ull;
-            }
-            if (threadIdx.x < kLabGroup) {
-                const int e = e0 + (int)threadIdx.x * G;
-                g.slot[threadIdx.x] = e < n ? f.tk_slot[e] : -1;
-                g.key[threadIdx.x] = e < n ? f.tk_key[e] : 0ull;
+            {  // all of the group's reads at once (clamped indices, masked after)
+                const int j = (threadIdx.x >> 3) & (kLabGroup - 1), k = threadIdx.x & 7;
+                const int ew = e0 + j * G, es = e0 + (int)(threadIdx.x & (kLabGroup - 1)) * G;
+                const bool okw = threadIdx.x < kLabGroup * 8 && ew < n, oks = es < n;
+                const unsigned long long wv = f.band[okw ? (size_t)ew * 8 + k : 0];
+                const int sv = f.tk_slot[oks ? es : 0];
+                const unsigned long long kv = f.tk_key[oks ? es : 0];
+                if (threadIdx.x < kLabGroup * 8) g.w[j][k] = okw ? wv : 0ull;
+                if (threadIdx.x < kLabGroup) {
+                    g.slot[threadIdx.x] = oks ? sv : -1;
+                    g.key[threadIdx.x] = oks ? kv : 0ull;
+                }
             }
             __syncthreads();
             if (threadIdx.x < kLabGroup) {
@@ -219,6 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
             epre[0] = 0;
 #pragma unroll
             for (int j = 0; j < kLabGroup; ++j) epre[j + 1] = epre[j] + g.pre[j][8];
+#pragma unroll 1
             for (int t = threadIdx.x; t < epre[kLabGroup]; t += kThreads) {
                 int j, li;
                 label_group_voxel(g, epre, t, j, li);
@@ -233,6 +238,7 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
             const int slot = f.tk_slot[e];
             const int3 bc = unpack_key(f.tk_key[e]);
             const BandWords b = band_words(f, e);
+#pragma unroll 1
             for (int t = lane; t < b.pre[8]; t += 64) my_votes += label_voxel(m, cs, slot, bc, band_select(b, t));
         }
     }
