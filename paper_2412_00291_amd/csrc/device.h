@@ -225,7 +225,10 @@ __device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapVie
 {
     const int k = pix / L.cols, c = pix - k * L.cols;
     const float r = range[pix];
-    const float ce = L.ce[k], se = L.se[k], cp = L.cp[c], sp = L.sp[c];  // read with the return
+    const float ce = L.ce[k], se = L.se[k], cp = L.cp[c], sp = L.sp[c];
+    // the table reads wait here with the return (else the compiler moves them past the
+    // validity test: a second round trip)
+    asm volatile("" ::"v"(r), "v"(ce), "v"(se), "v"(cp), "v"(sp));
     if (!valid_return(r, L.r_max)) return;
     const float dx = ce * cp, dy = ce * sp, dz = se;
     float s0 = r - m.tau;
@@ -426,10 +429,9 @@ __device__ __forceinline__ void hash_insert_new(const MapView &m, unsigned long 
 {
     uint32_t i = hash_slot(key, m.hmask);
     for (uint32_t n = 0; n <= m.hmask; ++n) {
-        unsigned long long prev = atomicCAS(&m.hkeys[i], kEmpty, key);
+        unsigned long long prev = atomicCAS(&m.hash[i].key, kEmpty, key);
         if (prev == kEmpty) {
-            m.hvals[i] = slot;
-            m.hframe[i] = frame_id;
+            *reinterpret_cast<uint2 *>(&m.hash[i].val) = make_uint2((uint32_t)slot, frame_id);
             return;
         }
         i = (i + 1) & m.hmask;
@@ -443,12 +445,9 @@ __device__ __forceinline__ int hash_find_old(const MapView &m, unsigned long lon
 {
     uint32_t i = hash_slot(key, m.hmask);
     for (uint32_t n = 0; n <= m.hmask; ++n) {
-        const unsigned long long k = m.hkeys[i];
-        if (k == key) {
-            const uint32_t fr = m.hframe[i];
-            return (fr == ~0u || fr == frame_id) ? -1 : m.hvals[i];
-        }
-        if (k == kEmpty) return -1;
+        const HashEntry h = hash_entry(&m.hash[i]);
+        if (h.key == key) return (h.frame == ~0u || h.frame == frame_id) ? -1 : h.val;
+        if (h.key == kEmpty) return -1;
         i = (i + 1) & m.hmask;
     }
     return -1;

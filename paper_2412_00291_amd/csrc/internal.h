@@ -53,15 +53,34 @@ struct SyncState {
     Spread votes;    // label votes since the last LiDAR frame
 };
 
+// One slot of the block hash, read with a single 16-byte load: the key (kEmpty: free),
+// the block's pool slot, and the integration call that inserted it (~0 until its
+// insertion completes).  Create fills every byte with 0xFF.
+struct __align__(16) HashEntry {
+    unsigned long long key;
+    int32_t val;
+    uint32_t frame;
+};
+
+// The whole entry in one 16-byte load (read field by field, the compiler would load the
+// slot only after the key compared equal: a second dependent round trip).
+__device__ __forceinline__ HashEntry hash_entry(const HashEntry *p)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    HashEntry h;
+    h.key = (unsigned long long)v.x | ((unsigned long long)v.y << 32);
+    h.val = (int32_t)v.z;
+    h.frame = v.w;
+    return h;
+}
+
 // Block pool, hash and dirty set.
 struct MapView {
     float2 *dw;               // [max_blocks][512] (D, W)
     uint8_t *fused;           // [max_blocks][512]
     uint16_t *counts;         // [max_blocks][L][512]
     int4 *coords;             // [max_blocks] block coordinates per slot
-    unsigned long long *hkeys;  // [hmask + 1]
-    int32_t *hvals;           // [hmask + 1]
-    uint32_t *hframe;         // [hmask + 1] integration call that inserted the key (~0: none)
+    HashEntry *hash;          // [hmask + 1]
     uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
     uint16_t *mesh_cnt;       // [max_blocks] triangles of a block in the current extraction
     int32_t *mesh_nbr;        // [max_blocks][8] slots of b + e, e in {0,1}^3 (-1: absent), same
@@ -173,9 +192,9 @@ __device__ inline int hash_find(const MapView &m, unsigned long long key)
 {
     uint32_t i = hash_slot(key, m.hmask);
     for (uint32_t n = 0; n <= m.hmask; ++n) {
-        unsigned long long k = m.hkeys[i];
-        if (k == key) return m.hvals[i];
-        if (k == kEmpty) return -1;
+        const HashEntry h = hash_entry(&m.hash[i]);
+        if (h.key == key) return h.val;
+        if (h.key == kEmpty) return -1;
         i = (i + 1) & m.hmask;
     }
     return -1;

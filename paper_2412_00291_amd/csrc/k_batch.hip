@@ -240,7 +240,7 @@ __device__ __forceinline__ void batch_lookup(const BatchMap *maps, const int *s_
             if (e == 0) S.bcs[jb] = v.coords[slot];
         } else {
             const int4 bc = v.coords[slot];
-            if (e == 0) S.bcs[jb] = bc;
+            if (e == 0) S.bcs[jb] = make_int4(bc.x, bc.y, bc.z, 0);  // .w unused: not read
             s = e == 0 ? slot : hash_find(v, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
             v.mesh_nbr[(size_t)slot * 8 + e] = s;
         }

@@ -118,7 +118,7 @@ __device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int
             if (e == 0) S.bcs[jb] = m.coords[slot];
         } else {
             const int4 bc = m.coords[slot];
-            if (e == 0) S.bcs[jb] = bc;
+            if (e == 0) S.bcs[jb] = make_int4(bc.x, bc.y, bc.z, 0);  // .w unused: not read
             s = e == 0 ? slot : hash_find(m, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
             m.mesh_nbr[(size_t)slot * 8 + e] = s;
         }

@@ -107,7 +107,7 @@ static void free_all(map_t *m)
     for (hipEvent_t e : m->prof_free) (void)hipEventDestroy(e);
     m->prof_pending.clear();
     m->prof_free.clear();
-    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hkeys, m->v.hvals, m->v.hframe,
+    void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hash,
                     m->v.dirty_flag, m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->lut_buf, m->partial, m->scan.wg_tris, m->scan.wg_blocks,
                     m->scan.wg_off};
@@ -250,9 +250,7 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&v.fused, nb * kBlockVoxels));
     CREATE_TRY(hipMalloc(&v.counts, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t)));
     CREATE_TRY(hipMalloc(&v.coords, nb * sizeof(int4)));
-    CREATE_TRY(hipMalloc(&v.hkeys, hcap * sizeof(unsigned long long)));
-    CREATE_TRY(hipMalloc(&v.hvals, hcap * sizeof(int32_t)));
-    CREATE_TRY(hipMalloc(&v.hframe, hcap * sizeof(uint32_t)));
+    CREATE_TRY(hipMalloc(&v.hash, hcap * sizeof(HashEntry)));
     CREATE_TRY(hipMalloc(&v.dirty_flag, nb * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.mesh_cnt, nb * sizeof(uint16_t)));
     CREATE_TRY(hipMalloc(&v.mesh_nbr, nb * 8 * sizeof(int32_t)));
@@ -273,9 +271,8 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMemsetAsync(v.dirty_flag, 0, nb * sizeof(uint32_t), s));
     CREATE_TRY(hipMemsetAsync(v.vmask, 0, nb * 16 * sizeof(unsigned long long), s));
     CREATE_TRY(hipMemsetAsync(v.sync, 0, sizeof(SyncState), s));
-    CREATE_TRY(hipMemsetAsync(v.hframe, 0xFF, hcap * sizeof(uint32_t), s));  // no insertion yet
+    CREATE_TRY(hipMemsetAsync(v.hash, 0xFF, hcap * sizeof(HashEntry), s));  // free keys, no insertion
     CREATE_TRY(launch_init_pool(v, s));
-    CREATE_TRY(launch_fill_u64(v.hkeys, hcap, kEmpty, s));
     std::memset(m->h_ctr, 0, sizeof(Counters));
     m->h_ctr->dirty_epoch = 1;
     CREATE_TRY(hipMemcpyAsync(v.ctr, m->h_ctr, sizeof(Counters), hipMemcpyHostToDevice, s));
