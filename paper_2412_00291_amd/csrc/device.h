@@ -156,21 +156,34 @@ __device__ __forceinline__ bool valid_return(float r, float r_max)
 
 // Claim a key in the frame set: 1 if this call inserted it (first in the frame), 0 if it
 // was there, -1 if the set is full.  Writes the set slot to *slot.
+__device__ __forceinline__ int frame_claim_from(const FrameView &f, unsigned long long key, uint32_t i, uint32_t n0,
+                                                uint32_t *slot)
+{
+    for (uint32_t n = n0; n <= f.fmask; ++n) {
+        const unsigned long long prev = atomicCAS(&f.fkeys[i], kEmpty, key);
+        if (prev == kEmpty) {
+            *slot = i;
+            return 1;
+        }
+        if (prev == key) return 0;
+        i = (i + 1) & f.fmask;
+    }
+    return -1;
+}
+
 __device__ __forceinline__ int frame_claim(const FrameView &f, unsigned long long key, uint32_t *slot)
 {
-    uint32_t i = hash_slot(key, f.fmask);
-    for (uint32_t n = 0; n <= f.fmask; ++n) {
-        unsigned long long cur = __atomic_load_n(&f.fkeys[i], __ATOMIC_RELAXED);
-        if (cur == key) return 0;
-        if (cur == kEmpty) {
-            unsigned long long prev = atomicCAS(&f.fkeys[i], kEmpty, key);
-            if (prev == kEmpty) {
-                *slot = i;
-                return 1;
-            }
-            if (prev == key) return 0;
-        }
-        i = (i + 1) & f.fmask;
+    return frame_claim_from(f, key, hash_slot(key, f.fmask), 0, slot);
+}
+
+// Slot of a key in the block hash, probing from slot i (probe n0 of the sequence).
+__device__ __forceinline__ int hash_find_from(const MapView &m, unsigned long long key, uint32_t i, uint32_t n0)
+{
+    for (uint32_t n = n0; n <= m.hmask; ++n) {
+        const HashEntry h = hash_entry(&m.hash[i]);
+        if (h.key == key) return h.val;
+        if (h.key == kEmpty) return -1;
+        i = (i + 1) & m.hmask;
     }
     return -1;
 }
@@ -312,10 +325,22 @@ __device__ __forceinline__ void alloc_flush(unsigned long long *lk, int *s_tmp, 
         mslot[j] = -2;  // not a winner
         if (i >= n_keys) continue;
         key[j] = lk[i];
-        const int c = frame_claim(f, key[j], &fslot[j]);
+        // the frame-set claim (a CAS at the key's first slot) and the block-hash probe are
+        // issued together; either continues past its first slot only on a collision
+        const uint32_t fi = hash_slot(key[j], f.fmask), hi = hash_slot(key[j], m.hmask);
+        const unsigned long long prev = atomicCAS(&f.fkeys[fi], kEmpty, key[j]);
+        const HashEntry h = hash_entry(&m.hash[hi]);
+        asm volatile("" ::"v"(prev), "v"(h.key), "v"(h.val));  // both results wait here together
+        int c;
+        if (prev == kEmpty) {
+            c = 1;
+            fslot[j] = fi;
+        } else {
+            c = prev == key[j] ? 0 : frame_claim_from(f, key[j], (fi + 1) & f.fmask, 1, &fslot[j]);
+        }
         if (c < 0) atomicExch(&m.ctr->overflow, 1);
         if (c <= 0) continue;
-        mslot[j] = hash_find(m, key[j]);
+        mslot[j] = h.key == key[j] ? h.val : (h.key == kEmpty ? -1 : hash_find_from(m, key[j], (hi + 1) & m.hmask, 1));
         n_win++;
         n_new += mslot[j] < 0;
     }
