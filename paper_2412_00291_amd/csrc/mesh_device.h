@@ -559,23 +559,40 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
 {
     __shared__ long long s_part[kThreads / 64];
     __shared__ long long s_blk[kThreads / 64];
-    constexpr int kPer = kMaxMeshGrid / kThreads;
+    constexpr int kPer = kMaxMeshGrid / kThreads;  // loads per thread: per * k <= kPer
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int per = (G + kThreads - 1) / kThreads;
     const int w0 = threadIdx.x * per;
+    // thread t sums emitting workgroups w0 .. w0 + per - 1, k counting workgroups each: the
+    // per * k counts are walked as (i, j) = (f / k, f mod k) in chunks of kPer loads issued
+    // together (one chunk unless the emitting grid is far from a multiple of kThreads);
+    // the first chunk's values are kept for the offsets
+    const int nf = per * k;
     long long v[kPer];
     long long sum = 0, blk = 0;
+    for (int f0 = 0; f0 < nf; f0 += kPer) {
+        int i = f0 / k, j = f0 - (f0 / k) * k;
+        long long t[kPer];
+        int b[kPer];
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        v[i] = 0;
-        if (i < per && w0 + i < G) {
-            for (int j = 0; j < k; ++j) {
-                const size_t idx = (size_t)(w0 + i + j * G) * stride;
-                v[i] += wg_tris[idx];
-                blk += wg_blocks[idx];
+        for (int f = 0; f < kPer; ++f) {
+            const bool ok = f0 + f < nf && w0 + i < G;
+            const size_t idx = ok ? (size_t)(w0 + i + j * G) * stride : 0;  // branch-free: entry 0, masked
+            t[f] = wg_tris[idx];
+            b[f] = wg_blocks[idx];
+            t[f] = ok ? t[f] : 0;
+            b[f] = ok ? b[f] : 0;
+            if (++j == k) {
+                j = 0;
+                ++i;
             }
         }
-        sum += v[i];
+#pragma unroll
+        for (int f = 0; f < kPer; ++f) {  // no use before every load is issued
+            sum += t[f];
+            blk += b[f];
+            if (f0 == 0) v[f] = t[f];
+        }
     }
     long long incl = sum;
 #pragma unroll
@@ -595,10 +612,18 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
         blocks += s_blk[w];
     }
     long long run = before + incl - sum;
+    for (int f0 = 0; f0 < nf; f0 += kPer) {
+        int i = f0 / k, j = f0 - (f0 / k) * k;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        if (i < per && w0 + i < G) wg_off[(size_t)(w0 + i) * stride] = run;
-        run += v[i];
+        for (int f = 0; f < kPer; ++f) {
+            const bool ok = f0 + f < nf && w0 + i < G;
+            if (ok && j == 0) wg_off[(size_t)(w0 + i) * stride] = run;
+            run += !ok ? 0 : (f0 == 0 ? v[f] : wg_tris[(size_t)(w0 + i + j * G) * stride]);
+            if (++j == k) {
+                j = 0;
+                ++i;
+            }
+        }
     }
     if (threadIdx.x == 0) {
         Counters *c = m.ctr;
