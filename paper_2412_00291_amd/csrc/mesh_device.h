@@ -568,6 +568,12 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
     // together (one chunk unless the emitting grid is far from a multiple of kThreads);
     // the first chunk's values are kept for the offsets
     const int nf = per * k;
+    Counters *c = m.ctr;
+    uint32_t epoch = 0, seq = 0;
+    if (threadIdx.x == 0) {  // read with the counts: used after the scan
+        epoch = c->dirty_epoch;
+        seq = c->extractions + 1;
+    }
     long long v[kPer];
     long long sum = 0, blk = 0;
     for (int f0 = 0; f0 < nf; f0 += kPer) {
@@ -612,13 +618,25 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
         blocks += s_blk[w];
     }
     long long run = before + incl - sum;
-    for (int f0 = 0; f0 < nf; f0 += kPer) {
-        int i = f0 / k, j = f0 - (f0 / k) * k;
+    {  // the first chunk from registers (no load between the offset stores)
+        int i = 0, j = 0;
 #pragma unroll
+        for (int f = 0; f < kPer; ++f) {
+            const bool ok = f < nf && w0 + i < G;
+            if (ok && j == 0) wg_off[(size_t)(w0 + i) * stride] = run;
+            run += ok ? v[f] : 0;
+            if (++j == k) {
+                j = 0;
+                ++i;
+            }
+        }
+    }
+    for (int f0 = kPer; f0 < nf; f0 += kPer) {  // further chunks are read again
+        int i = f0 / k, j = f0 - (f0 / k) * k;
         for (int f = 0; f < kPer; ++f) {
             const bool ok = f0 + f < nf && w0 + i < G;
             if (ok && j == 0) wg_off[(size_t)(w0 + i) * stride] = run;
-            run += !ok ? 0 : (f0 == 0 ? v[f] : wg_tris[(size_t)(w0 + i + j * G) * stride]);
+            run += ok ? wg_tris[(size_t)(w0 + i + j * G) * stride] : 0;
             if (++j == k) {
                 j = 0;
                 ++i;
@@ -626,13 +644,10 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
         }
     }
     if (threadIdx.x == 0) {
-        Counters *c = m.ctr;
-        const uint32_t epoch = c->dirty_epoch;
         c->mesh_epoch = epoch;
         c->mesh_tris = (unsigned long long)total;
         c->mesh_blocks = (unsigned long long)blocks;
         if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
-        const uint32_t seq = c->extractions + 1;
         c->extractions = seq;
         if (report) {  // host memory: system-scope stores; the host waits for seq, so it
                        // can return while the emitting pass still runs
