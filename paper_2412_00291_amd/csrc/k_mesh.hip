@@ -1,7 +1,8 @@
-// Marching cubes over the dirty (or all) blocks of one map, in three launches: count
-// triangles per workgroup, scan the counts (one workgroup, which also does the
-// extraction's bookkeeping), emit at the scanned offsets.  Both passes take the same
-// candidate blocks in the same order (see mesh_device.h), so the output is compact.
+// Marching cubes over the dirty (or all) blocks of one map, in two launches: count
+// triangles per workgroup, then emit, each emitting workgroup at the sum of the counts
+// before it (workgroup 0 also does the extraction's bookkeeping and the host report).
+// Both passes take the same candidate blocks in the same order (see mesh_device.h), so
+// the output is compact.
 #include "mesh_device.h"
 
 namespace mc {
@@ -10,28 +11,28 @@ __global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, Me
 {
     __shared__ MeshSmem<1, HaloMask> S;
     const Counters *c = m.ctr;
+    const uint32_t epoch = c->dirty_epoch;
     long long tris;
     int blocks;
-    mesh_count_wg(m, mode != 0, c->dirty_epoch, c->pool_used, S, &tris, &blocks);
+    mesh_count_wg(m, mode != 0, epoch, c->pool_used, S, &tris, &blocks);
     if (threadIdx.x == 0) {
         scan.wg_tris[blockIdx.x] = tris;
         scan.wg_blocks[blockIdx.x] = blocks;
+        if (blockIdx.x == 0) m.ctr->mesh_epoch = epoch;  // the emitting pass meshes this epoch
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_mesh_scan(MapView m, int mode, MeshScan scan, int G, int k, long long cap,
-                                                        MeshReport *report)
-{
-    mesh_scan_map(m, mode, scan.wg_tris, scan.wg_blocks, scan.wg_off, G, k, 1, cap, report);
-}
-
 template <int kSched>
-__global__ __launch_bounds__(kThreads) void k_mesh_emit(MapView m, int mode, MeshScan scan, MeshOut out)
+__global__ __launch_bounds__(kThreads) void k_mesh_emit(MapView m, int mode, MeshScan scan, MeshOut out, int g_count,
+                                                       MeshReport *report)
 {
     __shared__ MeshSmem<kSched, HaloFull> S;
     __shared__ MeshStage st;
+    __shared__ long long s_red[3 * (kThreads / 64)];
+    const TableRegs tab = mesh_tables_load<true>();  // in flight with the counts
+    const long long base = mesh_emit_base(m, mode, scan.wg_tris, scan.wg_blocks, g_count, out.cap, report, s_red);
     const Counters *c = m.ctr;
-    mesh_emit_wg<kSched>(m, mode != 0, c->mesh_epoch, c->pool_used, scan.wg_off[blockIdx.x], out, S, st);
+    mesh_emit_wg<kSched>(m, mode != 0, c->mesh_epoch, c->pool_used, base, out, S, st, tab);
 }
 
 MeshGrid mesh_grid(int schedule)
@@ -57,10 +58,10 @@ hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, co
 {
     if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
         return hipErrorInvalidValue;
-    const int k = grid.count / grid.emit;
-    hipLaunchKernelGGL(k_mesh_scan, dim3(1), dim3(kThreads), 0, s, m, mode, scan, grid.emit, k, out.cap, report);
-    if (schedule == 0) hipLaunchKernelGGL(k_mesh_emit<0>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
-    else hipLaunchKernelGGL(k_mesh_emit<1>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out);
+    if (schedule == 0)
+        hipLaunchKernelGGL(k_mesh_emit<0>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out, grid.count, report);
+    else
+        hipLaunchKernelGGL(k_mesh_emit<1>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out, grid.count, report);
     return hipGetLastError();
 }
 

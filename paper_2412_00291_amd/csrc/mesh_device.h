@@ -500,10 +500,10 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
 // (kSched 1); a round's output is contiguous, in wave order.
 template <int kSched>
 __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_t epoch, int nslots, long long base,
-                                             const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st)
+                                             const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st,
+                                             const TableRegs &tab)
 {
     constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
-    const TableRegs tab = mesh_tables_load<true>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int worker = kSched == 0 ? 0 : wave;
@@ -546,6 +546,85 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
         }
         __syncthreads();
     }
+}
+
+// The emitting workgroup's output offset, from the counting pass's per-workgroup counts:
+// emitting workgroup w takes the slots of counting workgroups c with c mod G = w, so its
+// offset sums the counts of those with c mod G < w.  Every thread calls it; the counts are
+// read at once (thread t takes t + q kThreads), clamped and masked.  Workgroup 0 (offset
+// 0) also sums every count and does the extraction's bookkeeping: totals, the epoch
+// advance that clears the dirty set when a DIRTY extraction fits (the counting pass has
+// read the epoch; the emitting pass meshes mesh_epoch, recorded by the counting pass),
+// and the host report, which therefore arrives while the rest of the pass still runs.
+__device__ __forceinline__ long long mesh_emit_base(const MapView &m, int mode, const long long *wg_tris,
+                                                    const int32_t *wg_blocks, int g_count, long long cap,
+                                                    MeshReport *report, long long *s_red)
+{
+    constexpr int kPer = kMaxMeshGrid / kThreads;
+    constexpr int kWaves = kThreads / 64;
+    const int G = (int)gridDim.x, w = (int)blockIdx.x;
+    const bool lead = w == 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    Counters *c = m.ctr;
+    uint32_t epoch = 0, seq = 0;
+    if (lead && threadIdx.x == 0) {
+        epoch = c->dirty_epoch;
+        seq = c->extractions + 1;
+    }
+    const float inv_g = 1.0f / (float)G;
+    long long v[kPer];
+    int b[kPer];
+    bool need[kPer], before[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int cw = (int)threadIdx.x + q * kThreads;
+        int r = cw - (int)((float)cw * inv_g) * G;  // cw mod G (the float quotient is off by at most one)
+        r += r < 0 ? G : 0;
+        r -= r >= G ? G : 0;
+        before[q] = cw < g_count && r < w;
+        need[q] = before[q] || (lead && cw < g_count);
+        const int idx = need[q] ? cw : 0;
+        v[q] = wg_tris[idx];
+        b[q] = wg_blocks[lead ? idx : 0];  // branch-free (other workgroups read entry 0, unused)
+    }
+    long long part = 0, tot = 0, blk = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        part += before[q] ? v[q] : 0;
+        tot += need[q] ? v[q] : 0;
+        blk += need[q] ? b[q] : 0;
+    }
+    part = (long long)wave_sum_u64((unsigned long long)part);
+    if (lead) {
+        tot = (long long)wave_sum_u64((unsigned long long)tot);
+        blk = (long long)wave_sum_u64((unsigned long long)blk);
+    }
+    if (lane == 0) {
+        s_red[wave] = part;
+        s_red[kWaves + wave] = tot;
+        s_red[2 * kWaves + wave] = blk;
+    }
+    __syncthreads();
+    long long off = 0, total = 0, blocks = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        off += s_red[i];
+        total += s_red[kWaves + i];
+        blocks += s_red[2 * kWaves + i];
+    }
+    if (lead && threadIdx.x == 0) {
+        c->mesh_tris = (unsigned long long)total;
+        c->mesh_blocks = (unsigned long long)blocks;
+        if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
+        c->extractions = seq;
+        if (report) {  // host memory: system-scope stores; the host waits for seq
+            __hip_atomic_store(&report->tris, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&report->blocks, (unsigned long long)blocks, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&report->seq, (unsigned long long)seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    return off;
 }
 
 // Exclusive scan of one map's counts per emitting workgroup (one workgroup): offsets,
