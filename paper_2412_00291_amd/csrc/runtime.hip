@@ -74,9 +74,9 @@ static int fail(map_t *m, int code, const char *fmt, ...)
                         __LINE__);                                                                \
     } while (0)
 
-// Wait for an extraction's report (written by the scan that follows the counting pass,
-// before the emitting pass runs) by polling host-mapped memory, so the call returns while
-// the triangles are still being emitted on the stream.  Every 64 polls the event recorded
+// Wait for an extraction's report (written early in the emitting pass by its first
+// workgroup; by the scan kernel in batched steps) by polling host-mapped memory, so the
+// call returns while the triangles are still being emitted on the stream.  Every 64 polls the event recorded
 // after the extraction is queried: a device error ends the wait, and so does the
 // extraction's completion without the expected report (hipErrorUnknown).
 static hipError_t wait_report(const MeshReport *r, uint32_t seq, hipEvent_t done)
