@@ -218,7 +218,9 @@ def map_integrate_labels_multi(handle, cams, labels_dev, T_wc, stream=None):
 
 
 def map_extract_mesh(handle, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=None):
-    """Returns (status, n_tris).  Capacity is taken from pos_dev ([cap, 3, 3] float32)."""
+    """Returns (status, n_tris).  Capacity is taken from pos_dev ([cap, 3, 3] float32).
+    Returns once the count is known; the triangles are written on the stream after that,
+    so later work on the same stream (or a stream synchronisation) sees them."""
     import torch
     cap = 0 if pos_dev is None else pos_dev.shape[0]
     if lab_dev is not None and lab_dev.shape[0] < cap:
