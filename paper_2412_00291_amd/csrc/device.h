@@ -56,11 +56,12 @@ __device__ __forceinline__ int wg_scan(int v, int *tmp, int *total)
 // exact predicates and the nearest pixel
 // ---------------------------------------------------------------------------------
 
-// sign of ax*qy - ay*qx: the fp64 products of fp32 operands are exact, so the sign of the
-// correctly rounded difference is exact
+// sign of ax*qy - ay*qx: the fp64 products of fp32 operands are exact, so one fused
+// multiply-add rounds the exact difference once (the same value as rounding the
+// difference of the two exact products) and its sign is exact
 __device__ __forceinline__ double cross64(float ax, float ay, float qx, float qy)
 {
-    return (double)ax * (double)qy - (double)ay * (double)qx;
+    return __builtin_fma((double)ax, (double)qy, -((double)ay * (double)qx));
 }
 
 // Column c holds points strictly counter-clockwise of boundary c+1 and clockwise of, or
@@ -536,8 +537,11 @@ __device__ __forceinline__ bool tsdf_update(const MapView &m, const LidarLUT &L,
     if (!valid_return(r, L.r_max)) return false;
     const float psi = r - dist;
     if (psi < -tau) return false;
-    float w = (psi + tau) / two_tau;
-    if (w > 1.0f) w = 1.0f;
+    // w = min((psi + tau) / 2 tau, 1): a dividend of at least 2 tau gives a quotient of at
+    // least 1 under any rounding, so the division is needed only below it
+    const float a = psi + tau;
+    float w = 1.0f;
+    if (a < two_tau) w = a / two_tau;
     if (w == 0.0f) return false;
     const float gam = psi < tau ? psi : tau;
     const float num = v.y * v.x + w * gam;
