@@ -489,11 +489,23 @@ __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f
     if (fs.ok && slot < 0) {
         slot = fs.used + f.tk_rank[e];
         const int3 bc = unpack_key(key);
-        m.coords[slot] = make_int4(bc.x, bc.y, bc.z, 0);
+        m.coords[slot] = make_int4(bc.x, bc.y, bc.z, (int)fs.epoch);  // a new block is dirty
         hash_insert_new(m, key, slot, frame_id);
         f.tk_slot[e] = slot;
     }
     return slot;
+}
+
+// Mark a block dirty: its coordinates' fourth component holds the epoch.
+__device__ __forceinline__ void mark_dirty(const MapView &m, int slot, uint32_t epoch)
+{
+    reinterpret_cast<int *>(&m.coords[slot])[3] = (int)epoch;
+}
+
+// Whether a block is dirty in epoch (one 4-byte read).
+__device__ __forceinline__ bool is_dirty(const MapView &m, int slot, uint32_t epoch)
+{
+    return (uint32_t)reinterpret_cast<const int *>(&m.coords[slot])[3] == epoch;
 }
 
 // Dirty set: the block and its allocated lower neighbours b - e, e in {0,1}^3 (a

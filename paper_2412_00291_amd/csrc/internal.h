@@ -79,9 +79,9 @@ struct MapView {
     float2 *dw;               // [max_blocks][512] (D, W)
     uint8_t *fused;           // [max_blocks][512]
     uint16_t *counts;         // [max_blocks][L][512]
-    int4 *coords;             // [max_blocks] block coordinates per slot
+    int4 *coords;             // [max_blocks] block coordinates per slot; .w: epoch of the block's
+                              // last dirty marking (dirty when it holds the current epoch)
     HashEntry *hash;          // [hmask + 1]
-    uint32_t *dirty_flag;     // [max_blocks] epoch of the last marking
     uint16_t *mesh_cnt;       // [max_blocks] triangles of a block in the current extraction
     int32_t *mesh_nbr;        // [max_blocks][8] slots of b + e, e in {0,1}^3 (-1: absent), same
     unsigned long long *vmask;  // [max_blocks][16] per z slice: sign bits (D < 0), then observed

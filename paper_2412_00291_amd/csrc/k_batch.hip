@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
                 if (fs.ok) {
                     const MapView &v = maps[mi].v;
                     const int s = neighbour_slot(v, rank & 7, unpack_key(maps[mi].f.tk_key[e]), si, maps[mi].frame_id);
-                    if (s >= 0) v.dirty_flag[s] = fs.epoch;
+                    if (s >= 0) mark_dirty(v, s, fs.epoch);
                 }
             }
         }
@@ -203,9 +203,9 @@ __device__ __forceinline__ int batch_candidates(const BatchMap *maps, const int 
     if (item < total) {
         const int mi = find_map(s_pre, n, (int)item);
         const MapView &v = maps[mi].v;
-        const uint32_t fl = v.dirty_flag[item - s_pre[mi]];
+        const bool dirty = is_dirty(v, item - s_pre[mi], s_epoch[mi]);
         const uint16_t nt = need_tris ? v.mesh_cnt[item - s_pre[mi]] : (uint16_t)1;
-        take = fl == s_epoch[mi] && nt != 0;
+        take = dirty && nt != 0;
     }
     const unsigned long long bal = __ballot(take);
     if (lane == 0) S.wcnt[wave] = __popcll(bal);

@@ -41,6 +41,7 @@ constexpr int kMeshBatch = kThreads / 8;
 constexpr int kTriRow = 3 * MC_MAX_TRIS;
 template <int kSched, class Halo>
 struct __align__(16) MeshSmem {
+    static constexpr bool kEmit = sizeof(Halo) == sizeof(HaloFull);  // the emitting pass's LDS
     uint8_t ntri[256];
     int8_t tris[sizeof(Halo) == sizeof(HaloFull) ? 256 * kTriRow : 4];
     Halo h[kSched == 0 ? 1 : kThreads / 64];
@@ -50,6 +51,7 @@ struct __align__(16) MeshSmem {
     int nbs[kMeshBatch][8];
     int mis[kMeshBatch];  // map of each batch entry (batched steps)
     int list[kThreads];
+    int4 lbc[kEmit ? 1 : kThreads];  // counting pass: the candidates' coordinates
     int wcnt[kThreads / 64];
     long long rcnt[kThreads / 64];
 };
@@ -103,22 +105,21 @@ __device__ __forceinline__ void worker_sync()
 }
 
 // Coordinates and neighbour slots (b + e, e in {0,1}^3; -1 when absent) of list entries
-// j0 .. j0 + nb - 1, nb <= kMeshBatch; every thread calls it.  The counting pass looks the
-// neighbours up in the hash and keeps them in mesh_nbr for the emitting pass, which
-// fetches them with one coalesced read per block.
+// j0 .. j0 + nb - 1, nb <= kMeshBatch; every thread calls it.  The counting pass has the
+// coordinates from its candidate scan, looks the neighbours up in the hash and keeps them
+// in mesh_nbr for the emitting pass, which fetches them with one coalesced read per block.
 template <class Smem>
-__device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int j0, int nb, bool fetch)
+__device__ __forceinline__ void mesh_batch_lookup(const MapView &m, Smem &S, int j0, int nb)
 {
     const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
     if (jb < nb) {
         const int slot = S.list[j0 + jb];
         int s;
-        if (fetch) {
+        if constexpr (Smem::kEmit) {
             s = m.mesh_nbr[(size_t)slot * 8 + e];
             if (e == 0) S.bcs[jb] = m.coords[slot];
         } else {
-            const int4 bc = m.coords[slot];
-            if (e == 0) S.bcs[jb] = make_int4(bc.x, bc.y, bc.z, 0);  // .w unused: not read
+            const int4 bc = S.lbc[j0 + jb];  // read by the candidate scan
             s = e == 0 ? slot : hash_find(m, pack_key(bc.x + (e & 1), bc.y + ((e >> 1) & 1), bc.z + ((e >> 2) & 1)));
             m.mesh_nbr[(size_t)slot * 8 + e] = s;
         }
@@ -422,11 +423,19 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
     if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= nslots) return -1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long slot = ((long long)it * kThreads + threadIdx.x) * gridDim.x + blockIdx.x;
+    constexpr bool kKeep = !Smem::kEmit;  // the counting pass keeps the coordinates it reads
     bool take = false;
+    int4 bc = make_int4(0, 0, 0, 0);
     if (slot < nslots) {  // both loads issued together (the count is only used for dirty slots)
-        const uint32_t fl = all ? epoch : m.dirty_flag[slot];
+        uint32_t fl;
+        if constexpr (kKeep) {
+            bc = m.coords[slot];
+            fl = (uint32_t)bc.w;
+        } else {
+            fl = (uint32_t)reinterpret_cast<const int *>(&m.coords[slot])[3];
+        }
         const uint16_t nt = need_tris ? m.mesh_cnt[slot] : (uint16_t)1;
-        take = fl == epoch && nt != 0;
+        take = (all || fl == epoch) && nt != 0;
     }
     const unsigned long long bal = __ballot(take);
     if (lane == 0) S.wcnt[wave] = __popcll(bal);
@@ -438,7 +447,11 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
         off += w < wave ? c : 0;
         n += c;
     }
-    if (take) S.list[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)slot;
+    if (take) {
+        const int at = off + __popcll(bal & ((1ull << lane) - 1ull));
+        S.list[at] = (int)slot;
+        if constexpr (kKeep) S.lbc[at] = bc;
+    }
     __syncthreads();
     return n;
 }
@@ -459,7 +472,7 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
-            mesh_batch_lookup(m, S, j0, nb, false);
+            mesh_batch_lookup(m, S, j0, nb);
             for (int j = wave; j < nb; j += kThreads / 64) {
                 mesh_stage_masks(m, S.nbs[j], S.h[wave], lane);
                 const unsigned long long t =
@@ -515,7 +528,7 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
             const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
-            mesh_batch_lookup(m, S, j0, nb, true);
+            mesh_batch_lookup(m, S, j0, nb);
             for (int r = 0; r < nb; r += kPerRound) {
                 const int j = r + worker;
                 const bool has = j < nb;

@@ -108,7 +108,7 @@ static void free_all(map_t *m)
     m->prof_pending.clear();
     m->prof_free.clear();
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hash,
-                    m->v.dirty_flag, m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
+                    m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->lut_buf, m->partial, m->scan.wg_tris, m->scan.wg_blocks,
                     m->scan.wg_off};
     for (void *p : ptrs)
@@ -251,7 +251,6 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&v.counts, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t)));
     CREATE_TRY(hipMalloc(&v.coords, nb * sizeof(int4)));
     CREATE_TRY(hipMalloc(&v.hash, hcap * sizeof(HashEntry)));
-    CREATE_TRY(hipMalloc(&v.dirty_flag, nb * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.mesh_cnt, nb * sizeof(uint16_t)));
     CREATE_TRY(hipMalloc(&v.mesh_nbr, nb * 8 * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&v.vmask, nb * 16 * sizeof(unsigned long long)));
@@ -268,7 +267,6 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMemsetAsync(v.dw, 0, nb * kBlockVoxels * sizeof(float2), s));
     CREATE_TRY(hipMemsetAsync(v.counts, 0, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t), s));
     CREATE_TRY(hipMemsetAsync(v.coords, 0, nb * sizeof(int4), s));
-    CREATE_TRY(hipMemsetAsync(v.dirty_flag, 0, nb * sizeof(uint32_t), s));
     CREATE_TRY(hipMemsetAsync(v.vmask, 0, nb * 16 * sizeof(unsigned long long), s));
     CREATE_TRY(hipMemsetAsync(v.sync, 0, sizeof(SyncState), s));
     CREATE_TRY(hipMemsetAsync(v.hash, 0xFF, hcap * sizeof(HashEntry), s));  // free keys, no insertion
