@@ -414,8 +414,8 @@ __device__ __forceinline__ int wave_scan_incl(int v)
 // returns their number, or -1 past the end.  Candidates are the map's slots [0, nslots),
 // dealt out one at a time: thread t of workgroup w takes slot (it kThreads + t) G + w,
 // so a cluster of dirty slots spreads over all workgroups.  A slot is taken if `all` or
-// its dirty flag holds `epoch`, and (need_tris: the emitting pass) the counting pass
-// found triangles in it.
+// its dirty mark (coordinates .w) holds `epoch`, and (need_tris: the emitting pass) the
+// counting pass found triangles in it.
 template <class Smem>
 __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint32_t epoch, int nslots, int it,
                                                bool need_tris, Smem &S)
