@@ -1,10 +1,11 @@
 // Marching cubes of 8^3 blocks (end of Sec. IV-C.3), in two passes over the same
-// candidate blocks: a counting pass (triangles per workgroup) and, after a scan of those
-// counts, an emitting pass that writes each block's triangles at its offset.  No
-// triangle reservation takes a shared atomic.  A worker (a workgroup, or a wavefront)
-// stages a block and its +1 halo (9^3 voxels of distance, weight and fused label,
-// ~6.6 KiB) in LDS from up to eight blocks, classifies the 512 cubes from the generated
-// case table, and emits vertices on the sign-change edges.
+// candidate blocks: a counting pass (triangles per workgroup, from the voxel masks) and an
+// emitting pass that writes each block's triangles at its offset, the prefix of those
+// counts (summed by each emitting workgroup itself, or by a scan launch in batched
+// steps).  No triangle reservation takes a shared atomic.  A worker (a workgroup, or a
+// wavefront) stages a block and its +1 halo (9^3 voxels of distance, weight and fused
+// label) in LDS from up to eight blocks, classifies the 512 cubes from the generated case
+// table, and emits vertices on the sign-change edges.
 #pragma once
 #include "device.h"
 #include "mc_table.inc"
@@ -640,7 +641,7 @@ __device__ __forceinline__ long long mesh_emit_base(const MapView &m, int mode, 
     return off;
 }
 
-// Exclusive scan of one map's counts per emitting workgroup (one workgroup): offsets,
+// Batched steps: exclusive scan of one map's counts per emitting workgroup (one workgroup): offsets,
 // and the extraction's bookkeeping.  Emitting workgroup w covers counting workgroups
 // w + j G, j < k; entry w of the arrays is at index w * stride.  A DIRTY extraction whose
 // output fits clears the dirty set by advancing the epoch; the emitting pass meshes the
