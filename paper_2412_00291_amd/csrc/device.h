@@ -64,6 +64,21 @@ __device__ __forceinline__ double cross64(float ax, float ay, float qx, float qy
     return __builtin_fma((double)ax, (double)qy, -((double)ay * (double)qx));
 }
 
+// Square root rounded to nearest (the value of sqrtf) of x >= 0.  The hardware root is
+// within one ulp of the root, so the rounded root is it or a neighbour: a neighbour s' is
+// taken when the residual x - s' s (one fused multiply-add) says the root lies beyond the
+// pair's geometric mean.  For x in [2^-64, FLT_MAX] the residuals stay normal numbers and
+// their signs are exact; other arguments take sqrtf.
+__device__ __forceinline__ float sqrt_rn(float x)
+{
+    if (!(x >= 0x1p-64f && x <= 3.40282347e38f)) return sqrtf(x);
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float sm = __int_as_float(__float_as_int(s) - 1), sp = __int_as_float(__float_as_int(s) + 1);
+    float r = fmaf(-sm, s, x) <= 0.0f ? sm : s;
+    r = fmaf(-sp, s, x) > 0.0f ? sp : r;
+    return r;
+}
+
 // Column c holds points strictly counter-clockwise of boundary c+1 and clockwise of, or
 // on, boundary c (boundary c lies between columns c-1 and c; ties go to the higher index).
 __device__ __forceinline__ bool col_holds(const LidarLUT &L, int c, float px, float py)
@@ -99,9 +114,11 @@ __device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float
     if (px == 0.0f && py == 0.0f) return false;
     const float kPi = 3.14159265358979f;
     const float a = (kPi - atan2_guess(py, px)) * L.cols_over_2pi;
+    // a is in [0, cols] up to the guess's error, so one wrap and a clamp give a valid start
+    // (the exact predicates decide the column; no integer division on this path)
     int g = (int)floorf(a + 0.5f);
-    g %= L.cols;
-    if (g < 0) g += L.cols;
+    g = g >= L.cols ? g - L.cols : g;
+    g = g < 0 ? 0 : (g >= L.cols ? L.cols - 1 : g);
     int c = -1;
     if (col_holds(L, g, px, py)) c = g;
     else {
@@ -121,7 +138,7 @@ __device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float
     // below boundary k+1 (reaching boundary rows: outside), or up until it is on or below
     // boundary k (passing boundary 0: outside).  The walk's end implies the field-of-view
     // test, so the common case takes two predicates.
-    const float rho = sqrtf(px * px + py * py);
+    const float rho = sqrt_rn(px * px + py * py);
     const int R = L.rows;
     int k = (int)floorf((L.el_top - atan2_guess(pz, rho)) * L.rows_over_fov);
     k = k < 0 ? 0 : (k > R - 1 ? R - 1 : k);
@@ -536,7 +553,7 @@ __device__ __forceinline__ int tsdf_project(const MapView &m, const LidarLUT &L,
     int row, col;
     if (px == 0.0f && py == 0.0f && pz == 0.0f) return -1;
     if (!nearest_pixel(L, px, py, pz, row, col)) return -1;
-    dist = sqrtf((px * px + py * py) + pz * pz);
+    dist = sqrt_rn((px * px + py * py) + pz * pz);
     return row * L.cols + col;
 }
 
