@@ -87,7 +87,7 @@ def algorithmic_bytes(kernel, s, rows, cols, cams):
 
 TRAFFIC_JSON = os.path.join("profiles", "street_64x2048_traffic.json")
 GROUPS = {"alloc": ("k_alloc",), "tsdf": ("k_tsdf<",), "labels": ("k_labels<",),
-          "mesh": ("k_mesh_count", "k_mesh_scan", "k_mesh_emit<")}
+          "mesh": ("k_mesh_count", "k_mesh_emit<")}
 
 
 def sources_sha256(root):
