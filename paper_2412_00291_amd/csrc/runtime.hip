@@ -33,6 +33,7 @@ struct map_s {
     MeshScan scan{};        // extraction scratch, kMaxMeshGrid workgroups
     uint32_t frame_id = 0;  // integration calls so far (tags hash insertions)
     int sched[3] = {0, 0, 0};  // TSDF, labels, meshing: 0 workgroup / 1 wavefront per block
+    int tsdf_grid = 1024;      // TSDF workgroups: six per compute unit of the map's device
     std::string err;
     // LiDAR look-up tables (device) and the model they were built for
     float *lut_buf = nullptr;
@@ -222,6 +223,11 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
 
     map_t *m = new map_s();
     m->p = p;
+    // Six TSDF workgroups per compute unit: measured on a street frame (64 x 2048 scan,
+    // 0.1 m voxels), four and seven per unit take 7% and 17% longer.
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p.device) == hipSuccess && cus > 0)
+        m->tsdf_grid = 6 * cus;
     hipStream_t s = (hipStream_t)stream;
     m->last_stream = s;
     const size_t nb = (size_t)p.max_blocks;
@@ -424,7 +430,7 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] { return launch_alloc(m->v, m->f, m->lut, T, range_dev, s); }));
     const uint32_t fid = m->frame_id++;
     HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
-        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, 1024), s);
+        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, m->tsdf_grid), s);
     }));
     m->last_stream = s;
     m->has_scan = true;
