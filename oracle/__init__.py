@@ -61,6 +61,8 @@ def _load():
         L.om_segment_blocks.argtypes = [P, P, P, I64]
         L.om_ray_segment.argtypes = [P, I, I, P, F, I, I, F, P, P, P]
         L.om_pixel_of.argtypes = [I, I, P, P, P, P]
+        L.om_range_image.restype = I64
+        L.om_range_image.argtypes = [I, I, P, F, P, I64, F, F, P, P]
         L.om_query_sdf.argtypes = [P, P, I64, P, P, P, I]
         L.om_pose_adjoint.argtypes = [P, P, P, I, I64, P, P, P, P]
         L.om_set_block.argtypes = [P, I, I, I, P, P, P]
@@ -102,6 +104,20 @@ def pixel_of(lidar_rows, lidar_cols, elev, p):
     r, c = ctypes.c_int(), ctypes.c_int()
     ok = L.om_pixel_of(lidar_rows, lidar_cols, _p(e), _p(pp), ctypes.byref(r), ctypes.byref(c))
     return (r.value, c.value) if ok else None
+
+
+def range_image(lidar_rows, lidar_cols, elev, r_max, pts, F=1.0, O=0.0):
+    """Depth and height images (Eq. 3) of sensor-frame points [n, 3]: (D, H, pixels written)."""
+    L = _load()
+    e = _f32(elev)
+    p = _f32(pts).reshape(-1, 3)
+    D = np.zeros((lidar_rows, lidar_cols), dtype=np.float32)
+    H = np.zeros((lidar_rows, lidar_cols), dtype=np.float32)
+    w = L.om_range_image(lidar_rows, lidar_cols, _p(e), float(r_max), _p(p), p.shape[0], float(F), float(O),
+                         _p(D), _p(H))
+    if w < 0:
+        raise ValueError("invalid scan model")
+    return D, H, int(w)
 
 
 class OracleMap:

@@ -14,6 +14,7 @@
  *   - recursive Bayes label filter (Eq. 6) with hard labels and a symmetric
  *     likelihood: the posterior's argmax equals the argmax of per-class vote counts
  *   - marching cubes, vertex label = the most probable label                (Sec. IV-C.3)
+ *   - measurement preprocessing: depth and height images of a point cloud  (Eq. 3)
  *
  * Arithmetic: every value that is stored in the map or decides which voxel, pixel or
  * block is touched is computed in IEEE binary32 with a fixed evaluation order and no
@@ -360,6 +361,56 @@ int om_pixel_of(int rows, int cols, const float *elev, const float *p, int *row,
     int ok = pixel_of(&t, p[0], p[1], p[2], row, col);
     lut_free(&t);
     return ok;
+}
+
+/* Measurement preprocessing (Eq. 3): the point cloud's depth and height images.  The
+ * paper gives the pixel as (pi - atan2(y, x)) / dphi and the elevation's offset over its
+ * spacing; a point here goes to the nearest pixel centre by the same exact predicates as
+ * the projective update, so a scan converted to points and back keeps every return at its
+ * pixel.  Several points on one pixel: the nearest is kept (ties: the first in input
+ * order), as a depth buffer does.  D = F r and H = F (z + O) with the scalars of Eq. 3. */
+static int valid_return(float r, float r_max);
+
+int64_t om_range_image(int rows, int cols, const float *elev, float r_max, const float *pts, int64_t n,
+                       float F, float O, float *D, float *H)
+{
+    lut t;
+    if (!lut_build(&t, rows, cols, elev)) return -1;
+    const int64_t np = (int64_t)rows * cols;
+    float *best = (float *)malloc(np * sizeof(float));
+    int64_t *who = (int64_t *)malloc(np * sizeof(int64_t));
+    for (int64_t q = 0; q < np; ++q) {
+        best[q] = INFINITY;
+        who[q] = -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) continue;
+        const float r = sqrtf((x * x + y * y) + z * z);
+        if (!valid_return(r, r_max)) continue;
+        int row, col;
+        if (!pixel_of(&t, x, y, z, &row, &col)) continue;
+        const int64_t q = (int64_t)row * cols + col;
+        if (r < best[q]) {
+            best[q] = r;
+            who[q] = i;
+        }
+    }
+    int64_t written = 0;
+    for (int64_t q = 0; q < np; ++q) {
+        if (who[q] < 0) {
+            D[q] = 0.0f;
+            if (H) H[q] = 0.0f;
+            continue;
+        }
+        D[q] = F * best[q];
+        if (H) H[q] = F * (pts[3 * who[q] + 2] + O);
+        ++written;
+    }
+    free(best);
+    free(who);
+    lut_free(&t);
+    return written;
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -71,6 +71,14 @@ int om_ray_segment(const omap *m, int rows, int cols, const float *elev, float r
 /* Pixel chosen for a sensor-frame point (for pins): returns 1 and row/col, or 0 if none. */
 int om_pixel_of(int rows, int cols, const float *elev, const float *p, int *row, int *col);
 
+/* Measurement preprocessing (Eq. 3): depth image D = F r and height image H = F (z + O)
+ * of a sensor-frame point cloud pts[n][3].  Each valid point (finite, 0 < r <= r_max,
+ * r = |p| in fp32) goes to its nearest pixel; a pixel keeps its nearest point, the lowest
+ * index among equal ranges.  Pixels with no point hold 0 in D and H.  H may be NULL.
+ * Returns the number of pixels written, or -1 for an invalid scan model. */
+int64_t om_range_image(int rows, int cols, const float *elev, float r_max, const float *pts, int64_t n,
+                       float F, float O, float *D, float *H);
+
 /* Trilinear SDF query.  mode 0: fp64 points and decisions; mode 1: the points are fp32
  * values and the cell is chosen from the fp32 quotient x / nu.  grad nullable. */
 void om_query_sdf(const omap *m, const double *pts, int64_t n, double *sdf, double *grad,
