@@ -250,6 +250,38 @@ def bench_adjoint(torch, reps=5):
                          "unit": "GB/s", "frac": bytes_ / (k_ms * 1e-3) / PEAK_HBM}}
 
 
+def bench_range_image(torch, reps=50):
+    """Measurement preprocessing: raw street point clouds (64 x 2048 scan, one return per
+    beam and column plus 10% second returns and 1% invalid points) to depth and height
+    images, the clouds resident in HBM."""
+    import synth
+    from paper_2412_00291_amd import KERNEL_NAMES, LidarModel, Map
+    w = synth.street_workload(n_frames=4, n_cams=1)
+    lidar = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
+    clouds = [torch.from_numpy(synth.cloud_points(w, k, 200 + k)).cuda() for k in range(4)]
+    D = torch.empty(w.lidar.rows, w.lidar.cols, device="cuda")
+    H = torch.empty_like(D)
+    m = Map(w.voxel, w.trunc, w.n_classes, 1 << 12)
+    for P in clouds:
+        m.range_image(lidar, P, D, H)
+    torch.cuda.synchronize()
+    m.profile(1 << KERNEL_NAMES.index("range"))
+    t0 = time.perf_counter()
+    for i in range(reps):
+        m.range_image(lidar, clouds[i % 4], D, H)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    prof = m.profile_read()["range"]
+    k_ms = prof[0] / max(prof[1], 1)
+    n = sum(int(clouds[i % 4].shape[0]) for i in range(reps)) / reps
+    bytes_ = 12 * n + 8 * w.lidar.rows * w.lidar.cols  # points in; depth and height out
+    m.close()
+    return {"workload": "street clouds, 64x2048 scan, ~145k points each", "points": n,
+            "ms_per_call": 1e3 * dt, "points_per_s": n / dt, "kernel_ms": k_ms,
+            "roofline": {"bound": "hbm", "achieved": bytes_ / (k_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": bytes_ / (k_ms * 1e-3) / PEAK_HBM}}
+
+
 def bench_batched(torch):
     """Batched form: 16 street maps of uneven size (voxel 0.05-0.4 m, 16/32/64 beams,
     1024-2048 columns, 4-8 frames each here, one 1280x720 camera), autotuned schedule,
@@ -558,7 +590,8 @@ def main():
         "roofline": roofline,
     }
     if not args.no_extensions:
-        result["extensions"] = {"pose_adjoint": bench_adjoint(torch), "batched": bench_batched(torch),
+        result["extensions"] = {"pose_adjoint": bench_adjoint(torch), "range_image": bench_range_image(torch),
+                                "batched": bench_batched(torch),
                                 "large_scale": bench_campus(torch)}
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

@@ -137,6 +137,21 @@ int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
  * only the speed differs.  Default 0, 0, 0. */
 int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
 
+/* Measurement preprocessing (Eq. 3): depth image D = F r and height image H = F (z + O)
+ * of n sensor-frame points (device float [n][3], undistorted), for the scan model L (the
+ * same model map_integrate_lidar takes; D is then a range image it accepts when F = 1).
+ * A point is valid when its coordinates are finite and 0 < r <= r_max, with r = |p|
+ * rounded to fp32 as (x^2 + y^2) + z^2 then a correctly rounded square root; a valid
+ * point goes to its nearest pixel (column c looks along azimuth pi - c 2pi/cols, row k
+ * along elev_rad[k]; the exact boundary rule of the projective update).  A pixel keeps
+ * its nearest point, the first in input order among equal ranges; pixels with no point
+ * hold 0.  Outputs (device, row-major [rows][cols] float): depth (required), height
+ * (nullable).  n <= 2^31 - 1.  The map contributes its device, look-up tables and a
+ * per-pixel scratch image (8 bytes a pixel, grown on demand); the map's contents are not
+ * read or changed.  Asynchronous. */
+int map_range_image(map_t *map, const lidar_model *L, const float *pts_dev, int64_t n, float F, float O,
+                    float *depth_dev, float *height_dev, void *stream);
+
 /* Trilinear query of the distance field at n world points (device float [n][3]):
  * sdf [n] float, grad [n][3] float (nullable), valid [n] uint8.  A point is valid when
  * all eight voxels around it are observed; invalid points get 0.  Asynchronous. */
@@ -211,7 +226,8 @@ const char *map_last_error(const map_t *map);
 #define MAP_K_QUERY 4      /* trilinear SDF query */
 #define MAP_K_ADJOINT 5    /* pose / point adjoint (both of its launches) */
 #define MAP_K_BATCH 6      /* batched multi-map step */
-#define MAP_KERNEL_COUNT 7
+#define MAP_K_RANGE 7      /* point cloud to depth and height images (both launches) */
+#define MAP_KERNEL_COUNT 8
 int map_profile(map_t *map, uint32_t mask);
 int map_profile_read(map_t *map, double *total_ms, int64_t *launches);
 

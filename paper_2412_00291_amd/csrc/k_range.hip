@@ -1,0 +1,62 @@
+// Measurement preprocessing (Eq. 3): a sensor-frame point cloud to its depth image
+// D = F r and height image H = F (z + O).  A point goes to its nearest pixel under the
+// exact predicates of the projective update, so a scan turned into points and back keeps
+// every return at its pixel.  A pixel keeps its nearest point and, among points of equal
+// range, the first in input order: each point takes one 64-bit atomic minimum of
+// (range bits << 32 | index) on its pixel's key (a non-negative float orders as its bit
+// pattern), then one pass over the pixels writes D and H and resets the keys.
+#include "device.h"
+
+namespace mc {
+
+constexpr unsigned long long kNoPoint = ~0ull;
+
+__global__ __launch_bounds__(kThreads) void k_range_scatter(LidarLUT L, const float *__restrict__ pts, int n,
+                                                            unsigned long long *keys)
+{
+    const int stride = (int)gridDim.x * kThreads;
+    for (int i = (int)blockIdx.x * kThreads + (int)threadIdx.x; i < n; i += stride) {
+        const float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
+        if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
+        const float r = sqrt_rn((x * x + y * y) + z * z);
+        if (!valid_return(r, L.r_max)) continue;
+        int row, col;
+        if (!nearest_pixel(L, x, y, z, row, col)) continue;
+        const unsigned long long key = ((unsigned long long)__float_as_uint(r) << 32) | (unsigned)i;
+        atomicMin(&keys[(size_t)row * L.cols + col], key);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_range_finish(unsigned long long *keys, int npix,
+                                                           const float *__restrict__ pts, float F, float O,
+                                                           float *__restrict__ depth, float *__restrict__ height)
+{
+    const int q = (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    if (q >= npix) return;
+    const unsigned long long key = keys[q];
+    keys[q] = kNoPoint;  // ready for the next call
+    float d = 0.0f, h = 0.0f;
+    if (key != kNoPoint) {
+        const unsigned i = (unsigned)(key & 0xFFFFFFFFull);
+        d = F * __uint_as_float((unsigned)(key >> 32));
+        h = F * (pts[3 * (size_t)i + 2] + O);
+    }
+    depth[q] = d;
+    if (height) height[q] = h;
+}
+
+hipError_t launch_range_image(const LidarLUT &lut, const float *pts, int n, float F, float O,
+                              unsigned long long *keys, float *depth, float *height, hipStream_t s)
+{
+    const int npix = lut.rows * lut.cols;
+    if (n > 0) {
+        const long long g = ((long long)n + kThreads - 1) / kThreads;
+        const int grid = g < 4096 ? (int)g : 4096;
+        hipLaunchKernelGGL(k_range_scatter, dim3(grid), dim3(kThreads), 0, s, lut, pts, n, keys);
+    }
+    hipLaunchKernelGGL(k_range_finish, dim3((npix + kThreads - 1) / kThreads), dim3(kThreads), 0, s, keys, npix,
+                       pts, F, O, depth, height);
+    return hipGetLastError();
+}
+
+}  // namespace mc

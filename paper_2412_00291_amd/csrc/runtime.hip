@@ -42,6 +42,11 @@ struct map_s {
     int lut_rows = 0, lut_cols = 0;
     float lut_rmax = 0.0f;
     std::vector<float> lut_elev;
+    // depth-buffer keys of the point-cloud preprocessing, one per pixel (all kNoPoint
+    // between calls: the finishing pass resets what it reads)
+    unsigned long long *rkeys = nullptr;
+    int64_t rkeys_n = 0;
+    bool rkeys_dirty = false;  // a failed call may have left keys set
     // adjoint partial sums
     float *partial = nullptr;
     size_t partial_floats = 0;
@@ -111,7 +116,7 @@ static void free_all(map_t *m)
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hash,
                     m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->lut_buf, m->partial, m->scan.wg_tris, m->scan.wg_blocks,
-                    m->scan.wg_off};
+                    m->scan.wg_off, m->rkeys};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (m->h_ctr) (void)hipHostFree(m->h_ctr);
@@ -519,6 +524,41 @@ extern "C" int map_set_schedule(map_t *m, int32_t tsdf, int32_t labels, int32_t 
     for (int i = 0; i < 3; ++i)
         if (v[i] != 0 && v[i] != 1) return fail(m, MAP_ERR_INVALID_ARG, "set_schedule: schedules are 0 or 1");
     for (int i = 0; i < 3; ++i) m->sched[i] = v[i];
+    return MAP_OK;
+}
+
+extern "C" int map_range_image(map_t *m, const lidar_model *L, const float *pts_dev, int64_t n, float F, float O,
+                               float *depth_dev, float *height_dev, void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (!L || !L->elev_rad || !depth_dev || n < 0 || n > INT32_MAX || (n > 0 && !pts_dev))
+        return fail(m, MAP_ERR_INVALID_ARG, "range_image: bad arguments");
+    if (!std::isfinite(F) || !std::isfinite(O)) return fail(m, MAP_ERR_INVALID_ARG, "range_image: F and O must be finite");
+    if (L->rows < 2 || L->cols < 8 || (int64_t)L->rows * L->cols > INT32_MAX)
+        return fail(m, MAP_ERR_INVALID_ARG, "range_image: need rows >= 2, cols >= 8, rows * cols < 2^31");
+    if (!(L->r_max > 0.0f) || !std::isfinite(L->r_max))
+        return fail(m, MAP_ERR_INVALID_ARG, "range_image: r_max must be positive and finite");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    const int rc = ensure_lut(m, L, s);
+    if (rc) return rc;
+    const int64_t npix = (int64_t)L->rows * L->cols;
+    if (npix > m->rkeys_n) {
+        HIP_TRY(m, hipDeviceSynchronize());  // an earlier call may still use the old keys
+        if (m->rkeys) HIP_TRY(m, hipFree(m->rkeys));
+        m->rkeys = nullptr;
+        m->rkeys_n = 0;
+        HIP_TRY(m, hipMalloc(&m->rkeys, (size_t)npix * sizeof(unsigned long long)));
+        m->rkeys_n = npix;
+        m->rkeys_dirty = true;
+    }
+    if (m->rkeys_dirty) HIP_TRY(m, launch_fill_u64(m->rkeys, (size_t)m->rkeys_n, ~0ull, s));
+    m->rkeys_dirty = true;
+    HIP_TRY(m, timed(m, MAP_K_RANGE, s, [&] {
+        return launch_range_image(m->lut, pts_dev, (int)n, F, O, m->rkeys, depth_dev, height_dev, s);
+    }));
+    m->rkeys_dirty = false;
+    m->last_stream = s;
     return MAP_OK;
 }
 

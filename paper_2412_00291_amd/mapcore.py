@@ -72,6 +72,8 @@ _sig = {
     "map_integrate_labels_multi": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P]),
     "map_extract_mesh": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
     "map_query_sdf": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    "map_range_image": (ctypes.c_int, [_P, ctypes.POINTER(_Lidar), _P, _I64, ctypes.c_float, ctypes.c_float, _P, _P,
+                                       _P]),
     "map_sdf_pose_adjoint": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
     "map_sync": (ctypes.c_int, [_P]),
     "map_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
@@ -89,7 +91,7 @@ _sig = {
     "map_profile_read": (ctypes.c_int, [_P, _P, _P]),
 }
 
-KERNEL_NAMES = ["alloc", "tsdf", "labels", "mesh", "query", "adjoint", "batch"]
+KERNEL_NAMES = ["alloc", "tsdf", "labels", "mesh", "query", "adjoint", "batch", "range"]
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
@@ -235,6 +237,20 @@ def map_extract_mesh(handle, mode, pos_dev, lab_dev, edge_keys_dev=None, stream=
     return st, n.value
 
 
+def map_range_image(handle, lidar: LidarModel, pts_dev, depth_dev, height_dev=None, F=1.0, O=0.0, stream=None):
+    """Depth and height images (Eq. 3) of sensor-frame points pts_dev [n, 3] float32 into
+    depth_dev (and height_dev, if given) [rows, cols] float32 device tensors."""
+    import torch
+    L = lidar._c()
+    npix = lidar.rows * lidar.cols
+    if depth_dev.numel() != npix or (height_dev is not None and height_dev.numel() != npix):
+        raise ValueError("image size does not match the LiDAR model")
+    n = pts_dev.shape[0]
+    return _lib.map_range_image(handle, ctypes.byref(L), _dev(pts_dev, torch.float32, "pts", 3) if n else None, n,
+                                float(F), float(O), _dev(depth_dev, torch.float32, "depth"),
+                                _dev(height_dev, torch.float32, "height"), _stream(stream))
+
+
 def map_query_sdf(handle, pts_dev, sdf_dev, grad_dev, valid_dev, stream=None):
     import torch
     n = pts_dev.shape[0]
@@ -368,6 +384,9 @@ class Map:
         st, n = map_extract_mesh(self.h, mode, pos_dev, lab_dev, edge_keys_dev, stream)
         self._check(st, (MAP_OK, MAP_ERR_BUFFER_TOO_SMALL) if allow_small else (MAP_OK,))
         return st, n
+
+    def range_image(self, lidar, pts_dev, depth_dev, height_dev=None, F=1.0, O=0.0, stream=None):
+        return self._check(map_range_image(self.h, lidar, pts_dev, depth_dev, height_dev, F, O, stream))
 
     def query_sdf(self, pts_dev, sdf_dev, grad_dev, valid_dev, stream=None):
         return self._check(map_query_sdf(self.h, pts_dev, sdf_dev, grad_dev, valid_dev, stream))

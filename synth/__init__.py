@@ -437,6 +437,46 @@ def scan_points(w: Workload, lidar: Lidar, frame_pose, n_points, seed):
     return pts.astype(np.float32)
 
 
+def cloud_points(w: Workload, k: int, seed: int, jitter=0.45, extra=0.1, invalid=0.01):
+    """Raw sensor-frame point cloud of frame k (float32 [n, 3], shuffled): one return per
+    beam and column cast at an angle drawn uniformly within +-jitter of a pixel spacing
+    around the pixel centre, with the workload's range noise; plus a fraction `extra` of
+    second returns (nearer and farther along drawn returns' directions) and a fraction
+    `invalid` of points no scan keeps (non-finite, at the origin, beyond r_max, above the
+    field of view)."""
+    lidar = w.lidar
+    R, C = lidar.rows, lidar.cols
+    rng = np.random.Generator(np.random.PCG64(seed))
+    e = lidar.elev_rad.astype(np.float64)
+    de = np.abs(np.diff(e))
+    de = np.concatenate([de[:1], de])  # spacing at each row
+    row = np.repeat(np.arange(R), C)
+    col = np.tile(np.arange(C), R)
+    el = e[row] + rng.uniform(-jitter, jitter, R * C) * de[row]
+    dphi = 2.0 * np.pi / C
+    phi = np.pi - col * dphi + rng.uniform(-jitter, jitter, R * C) * dphi
+    d = np.stack([np.cos(el) * np.cos(phi), np.cos(el) * np.sin(phi), np.sin(el)], axis=1)
+    Td = w.poses[k].astype(np.float64)
+    t, _ = w.scene.cast(Td[:3, 3], d @ Td[:3, :3].T, lidar.r_max)
+    ok = np.isfinite(t) & (t <= lidar.r_max)
+    r = t[ok] + rng.normal(0.0, w.noise_sigma, size=int(ok.sum()))
+    pts = d[ok] * r[:, None]
+    m = int(extra * len(pts))
+    pick = rng.choice(len(pts), size=m)
+    scale = np.where(rng.random(m) < 0.5, rng.uniform(0.5, 0.95, m), rng.uniform(1.05, 2.0, m))
+    more = pts[pick] * scale[:, None]
+    q = max(int(invalid * len(pts)), 8)
+    bad = np.zeros((q, 3))
+    kind = np.arange(q) % 4
+    bad[kind == 0] = np.nan
+    far = d[rng.choice(R * C, size=int((kind == 2).sum()))] * (lidar.r_max * 1.5)
+    bad[kind == 2] = far
+    up = np.deg2rad(80.0)
+    bad[kind == 3] = np.array([np.cos(up), 0.0, np.sin(up)]) * 5.0
+    allp = np.concatenate([pts, more, bad])
+    return allp[rng.permutation(len(allp))].astype(np.float32)
+
+
 def perturbed_poses(n, seed, rot_sigma=0.05, trans_sigma=0.2):
     """n pose 6-vectors (t, omega) drawn around the identity, float32 [n,6]."""
     rng = np.random.Generator(np.random.PCG64(seed))
