@@ -163,6 +163,33 @@ __device__ __forceinline__ bool nearest_pixel(const LidarLUT &L, float px, float
     return true;
 }
 
+// Copy the boundary tables (column boundaries, then row boundaries) into the workgroup's
+// LDS and point L at the copy; every thread calls it.  Every load of a chunk is in flight
+// at once (2560 pairs per chunk: one chunk for 2048 columns).
+__device__ __forceinline__ void stage_lut(LidarLUT &L, float2 *s_lut)
+{
+    constexpr int kPer = 10;
+    const int nc = L.cols, n = L.cols + L.rows + 1;
+    for (int i0 = 0; i0 < n; i0 += kPer * kThreads) {
+        float2 v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = i0 + k * kThreads + (int)threadIdx.x;
+            const float2 *src = i < nc ? L.bc + i : L.br + (i - nc);  // one load per element
+            v[k] = make_float2(0.0f, 0.0f);
+            if (i < n) v[k] = *src;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = i0 + k * kThreads + (int)threadIdx.x;
+            if (i < n) s_lut[i] = v[k];
+        }
+    }
+    L.bc = s_lut;
+    L.br = s_lut + nc;
+    __syncthreads();
+}
+
 __device__ __forceinline__ bool valid_return(float r, float r_max)
 {
     return isfinite(r) && r > 0.0f && r <= r_max;

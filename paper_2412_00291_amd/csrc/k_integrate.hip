@@ -91,29 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
     __shared__ int s_slot[kThreads / 8];
     __shared__ int s_last;
     __shared__ unsigned long long s_sum[kThreads / 64];
-    if (kLdsLut) {
-        // every load of a chunk in flight at once (2560 pairs per chunk: one for 2048 columns)
-        constexpr int kPer = 10;
-        const int nc = L.cols, n = L.cols + L.rows + 1;
-        for (int i0 = 0; i0 < n; i0 += kPer * kThreads) {
-            float2 v[kPer];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int i = i0 + k * kThreads + (int)threadIdx.x;
-                const float2 *src = i < nc ? L.bc + i : L.br + (i - nc);  // one load per element
-                v[k] = make_float2(0.0f, 0.0f);
-                if (i < n) v[k] = *src;
-            }
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int i = i0 + k * kThreads + (int)threadIdx.x;
-                if (i < n) s_lut[i] = v[k];
-            }
-        }
-        L.bc = s_lut;
-        L.br = s_lut + nc;
-        __syncthreads();
-    }
+    if (kLdsLut) stage_lut(L, s_lut);
     const FrameState fs = frame_state(m, f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;

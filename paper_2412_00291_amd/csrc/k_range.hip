@@ -52,6 +52,8 @@ hipError_t launch_range_image(const LidarLUT &lut, const float *pts, int n, floa
     if (n > 0) {
         const long long g = ((long long)n + kThreads - 1) / kThreads;
         const int grid = g < 4096 ? (int)g : 4096;
+        // the boundary tables are read through the caches: staging them in LDS per
+        // workgroup measured no faster at a street cloud's size
         hipLaunchKernelGGL(k_range_scatter, dim3(grid), dim3(kThreads), 0, s, lut, pts, n, keys);
     }
     hipLaunchKernelGGL(k_range_finish, dim3((npix + kThreads - 1) / kThreads), dim3(kThreads), 0, s, keys, npix,
