@@ -148,7 +148,9 @@ int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
  * hold 0.  Outputs (device, row-major [rows][cols] float): depth (required), height
  * (nullable).  n <= 2^31 - 1.  The map contributes its device, look-up tables and a
  * per-pixel scratch image (8 bytes a pixel, grown on demand); the map's contents are not
- * read or changed.  Asynchronous. */
+ * read or changed.  Asynchronous, except that a scan model other than the one the map's
+ * tables were last built for rebuilds them after synchronising the stream (as
+ * map_integrate_lidar does); growing the scratch image synchronises the device. */
 int map_range_image(map_t *map, const lidar_model *L, const float *pts_dev, int64_t n, float F, float O,
                     float *depth_dev, float *height_dev, void *stream);
 
