@@ -61,6 +61,7 @@ def _load():
         L.om_segment_blocks.argtypes = [P, P, P, I64]
         L.om_ray_segment.argtypes = [P, I, I, P, F, I, I, F, P, P, P]
         L.om_pixel_of.argtypes = [I, I, P, P, P, P]
+        L.om_integrate_labels_lidar.argtypes = [P, I, I, P, P, P]
         L.om_range_image.restype = I64
         L.om_range_image.argtypes = [I, I, P, F, P, I64, F, F, P, P]
         L.om_query_sdf.argtypes = [P, P, I64, P, P, P, I]
@@ -153,6 +154,13 @@ class OracleMap:
         T = _f32(T_wc).reshape(16)
         return self._L.om_integrate_labels(self.h, cam.width, cam.height, cam.fx, cam.fy, cam.cx,
                                            cam.cy, _p(lab), _p(T))
+
+    def integrate_labels_lidar(self, lidar, labels, T_wl) -> int:
+        e = _f32(lidar.elev_rad)
+        lab = np.ascontiguousarray(labels, dtype=np.uint8)
+        assert lab.size == lidar.rows * lidar.cols
+        T = _f32(T_wl).reshape(16)
+        return self._L.om_integrate_labels_lidar(self.h, lidar.rows, lidar.cols, _p(e), _p(lab), _p(T))
 
     def extract_mesh(self, mode=MESH_DIRTY, cap=None, with_keys=True):
         """Returns (status, pos [T,3,3] f32, labels [T,3] u8, keys [T,3] i64 or None, n)."""

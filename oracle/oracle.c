@@ -15,6 +15,7 @@
  *     likelihood: the posterior's argmax equals the argmax of per-class vote counts
  *   - marching cubes, vertex label = the most probable label                (Sec. IV-C.3)
  *   - measurement preprocessing: depth and height images of a point cloud  (Eq. 3)
+ *   - labels of the scan's points as a label range image                    (Sec. V-A)
  *
  * Arithmetic: every value that is stored in the map or decides which voxel, pixel or
  * block is touched is computed in IEEE binary32 with a fixed evaluation order and no
@@ -661,6 +662,20 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
 /* label fusion (Eq. 6 as vote counts) against the last scan                            */
 /* ------------------------------------------------------------------------------------ */
 
+/* One vote for label l at voxel li (Eq. 6 with hard labels): the count saturates at
+ * 65535 and the most probable label moves to l when l's count passes the current one's,
+ * or equals it with a lower id. */
+static void vote(oblock *b, int li, int l)
+{
+    uint16_t *cnt = b->counts;
+    unsigned c = cnt[(size_t)l * BLOCK_VOXELS + li];
+    if (c < 65535u) c++;
+    cnt[(size_t)l * BLOCK_VOXELS + li] = (uint16_t)c;
+    int f = b->fused[li];
+    unsigned cf = (f == 255) ? 0u : cnt[(size_t)f * BLOCK_VOXELS + li];
+    if (l != f && (c > cf || (c == cf && l < f))) b->fused[li] = (uint8_t)l;
+}
+
 int om_integrate_labels(omap *m, int width, int height, float fx, float fy, float cx, float cy,
                         const uint8_t *labels, const float *T)
 {
@@ -692,16 +707,53 @@ int om_integrate_labels(omap *m, int width, int height, float fx, float fy, floa
             int iu = (int)u, iv = (int)v; /* floor of a non-negative value */
             int l = labels[(size_t)iv * width + iu];
             if (l >= m->L) continue;
-            uint16_t *cnt = b->counts;
-            unsigned c = cnt[(size_t)l * BLOCK_VOXELS + li];
-            if (c < 65535u) c++;
-            cnt[(size_t)l * BLOCK_VOXELS + li] = (uint16_t)c;
-            int f = b->fused[li];
-            unsigned cf = (f == 255) ? 0u : cnt[(size_t)f * BLOCK_VOXELS + li];
-            if (l != f && (c > cf || (c == cf && l < f))) b->fused[li] = (uint8_t)l;
+            vote(b, li, l);
             votes++;
         }
     }
+    m->st.votes += votes;
+    return OM_OK;
+}
+
+/* Labels of the scan's points as a label range image (the semantic measurements of the
+ * paper's LiDAR-segmentation experiments, Sec. V-A): each visible voxel of the last scan
+ * takes the label at its nearest pixel of the scan model under pose T (the pixel rule of
+ * the projective update) and votes as a camera label does. */
+int om_integrate_labels_lidar(omap *m, int rows, int cols, const float *elev, const uint8_t *labels,
+                              const float *T)
+{
+    if (!m || !labels || !T || !elev) return OM_INVALID;
+    if (!check_pose(T)) return OM_INVALID;
+    lut t;
+    if (!lut_build(&t, rows, cols, elev)) return OM_INVALID;
+    if (!m->has_scan) {
+        lut_free(&t);
+        return OM_NO_SCAN;
+    }
+    const float nu = m->nu;
+    const float tx = T[3], ty = T[7], tz = T[11];
+    int64_t votes = 0;
+    for (int64_t i = 0; i < m->ntouched; ++i) {
+        oblock *b = m->blocks[m->touched[i]];
+        for (int li = 0; li < BLOCK_VOXELS; ++li) {
+            if (!b->band[li] || !(b->W[li] > 0.0f)) continue;
+            int lx = li & 7, ly = (li >> 3) & 7, lz = li >> 6;
+            float x = (float)(8 * b->b[0] + lx) * nu;
+            float y = (float)(8 * b->b[1] + ly) * nu;
+            float z = (float)(8 * b->b[2] + lz) * nu;
+            float dx = x - tx, dy = y - ty, dz = z - tz;
+            float px = (T[0] * dx + T[4] * dy) + T[8] * dz;
+            float py = (T[1] * dx + T[5] * dy) + T[9] * dz;
+            float pz = (T[2] * dx + T[6] * dy) + T[10] * dz;
+            int row, col;
+            if (!pixel_of(&t, px, py, pz, &row, &col)) continue;
+            int l = labels[(size_t)row * cols + col];
+            if (l >= m->L) continue;
+            vote(b, li, l);
+            votes++;
+        }
+    }
+    lut_free(&t);
     m->st.votes += votes;
     return OM_OK;
 }

@@ -48,6 +48,10 @@ int om_integrate_labels(omap *m, int width, int height, float fx, float fy, floa
                         const uint8_t *labels, const float *T_wc);
 /* Triangle soup: pos [3*cap][3] fp32, lab [3*cap], ekey [3*cap] (nullable).
  * *n_tris receives the count (also when the buffer is too small: OM_BUFFER). */
+/* Label range image (rows x cols uint8, the scan model's pixel layout) under pose T:
+ * each visible voxel of the last scan votes with the label at its nearest pixel. */
+int om_integrate_labels_lidar(omap *m, int rows, int cols, const float *elev, const uint8_t *labels,
+                              const float *T);
 int om_extract_mesh(omap *m, int mode, int64_t cap_tris, float *pos, uint8_t *lab, int64_t *ekey,
                     int64_t *n_tris);
 

@@ -218,6 +218,21 @@ class Workload:
         return Frame(T, rng_img, cams)
 
 
+    def lidar_labels(self, k: int, flip: float = 0.05) -> np.ndarray:
+        """Label range image of frame k (uint8 [rows, cols], the range image's layout): the
+        class of each LiDAR ray's first hit (255 on a miss), a fraction `flip` of the hits
+        replaced by a uniformly drawn class, as a point-cloud segmentation would give."""
+        Td = self.poses[k].astype(np.float64)
+        d = self.lidar.directions() @ Td[:3, :3].T
+        t, cl = self.scene.cast(Td[:3, 3], d, self.lidar.r_max)
+        lab = np.where(np.isfinite(t) & (t <= self.lidar.r_max), cl, 255).astype(np.int64)
+        rng = np.random.Generator(np.random.PCG64(self.seed * 1000 + 500 + k))
+        hit = lab != 255
+        flip_m = hit & (rng.random(lab.shape) < flip)
+        lab[flip_m] = rng.integers(0, self.n_classes, size=int(flip_m.sum()))
+        return lab.astype(np.uint8).reshape(self.lidar.rows, self.lidar.cols)
+
+
 # ----------------------------------------------------------------------------------------
 # Scene recipes
 # ----------------------------------------------------------------------------------------
