@@ -282,6 +282,37 @@ def bench_range_image(torch, reps=50):
                          "unit": "GB/s", "frac": bytes_ / (k_ms * 1e-3) / PEAK_HBM}}
 
 
+def bench_lidar_labels(torch, frames=24):
+    """Label fusion from label range images (the scan's points labelled by a segmentation
+    network): street frames, each integrated (64 x 2048 scan) and then fused with its
+    label range image; the label call alone is timed with events."""
+    import synth
+    from paper_2412_00291_amd import KERNEL_NAMES, LidarModel, Map
+    w = synth.street_workload(n_frames=frames, n_cams=1)
+    lidar = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
+    data = [(torch.from_numpy(w.frame(k, with_labels=False).range).cuda(),
+             torch.from_numpy(w.lidar_labels(k)).cuda(), w.poses[k]) for k in range(frames)]
+    m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    votes, warm = 0, 4
+    for k, (rng, lab, T) in enumerate(data):
+        if k == warm:
+            torch.cuda.synchronize()
+            m.profile(1 << KERNEL_NAMES.index("labels"))
+        m.integrate_lidar(lidar, rng, T)
+        m.integrate_labels_lidar(lidar, lab, T)
+        if k >= warm:
+            votes += m.stats()[1]["votes"]
+    prof = m.profile_read()["labels"]
+    m.close()
+    k_ms = prof[0] / max(prof[1], 1)
+    per = votes / max(prof[1], 1)
+    bytes_ = 8 * per + w.lidar.rows * w.lidar.cols
+    return {"workload": "street frames, 64x2048 label range images, L=19", "frames_timed": frames - warm,
+            "votes_per_frame": per, "kernel_ms": k_ms, "votes_per_s": per / (k_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": bytes_ / (k_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": bytes_ / (k_ms * 1e-3) / PEAK_HBM}}
+
+
 def bench_batched(torch):
     """Batched form: 16 street maps of uneven size (voxel 0.05-0.4 m, 16/32/64 beams,
     1024-2048 columns, 4-8 frames each here, one 1280x720 camera), autotuned schedule,
@@ -591,6 +622,7 @@ def main():
     }
     if not args.no_extensions:
         result["extensions"] = {"pose_adjoint": bench_adjoint(torch), "range_image": bench_range_image(torch),
+                                "lidar_labels": bench_lidar_labels(torch),
                                 "batched": bench_batched(torch),
                                 "large_scale": bench_campus(torch)}
     if not args.no_cpu_baseline:

@@ -137,6 +137,19 @@ int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
  * only the speed differs.  Default 0, 0, 0. */
 int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
 
+/* Label fusion from a label range image: the scan's points labelled by a point-cloud
+ * segmentation network, the semantic measurements of the paper's LiDAR experiments
+ * (Sec. V-A).  labels_dev: device uint8 [rows][cols] in the pixel layout of the scan model
+ * L (as the range image); T_wl the scan's pose (host float row-major 4x4).  Every voxel
+ * that the last accepted LiDAR frame updated within the truncation band (as for camera
+ * labels) takes the label at its nearest pixel (the pixel rule of the projective update)
+ * and votes as a camera label does (Eq. 6 with hard labels); labels >= n_classes (255 =
+ * none) do not vote.  MAP_ERR_NO_SCAN before any LiDAR frame.  Asynchronous; a scan model
+ * other than the one the map's tables were last built for rebuilds them after
+ * synchronising the stream. */
+int map_integrate_labels_lidar(map_t *map, const lidar_model *L, const uint8_t *labels_dev,
+                               const float T_wl[16], void *stream);
+
 /* Measurement preprocessing (Eq. 3): depth image D = F r and height image H = F (z + O)
  * of n sensor-frame points (device float [n][3], undistorted), for the scan model L (the
  * same model map_integrate_lidar takes; D is then a range image it accepts when F = 1).

@@ -9,7 +9,7 @@ from .mapcore import (  # noqa: F401
     MAP_ERR_DEVICE, MAP_MESH_DIRTY, MAP_MESH_ALL, MapError, Map, LidarModel, CameraModel, lib_path,
     map_create, map_destroy, map_integrate_lidar, map_integrate_labels, map_integrate_labels_multi,
     map_extract_mesh,
-    map_query_sdf, map_range_image, map_sdf_pose_adjoint, map_sync, map_stats, map_last_error, map_block_coords,
+    map_query_sdf, map_range_image, map_integrate_labels_lidar, map_sdf_pose_adjoint, map_sync, map_stats, map_last_error, map_block_coords,
     map_touched_coords, map_download, map_read_block, map_profile, map_profile_read, KERNEL_NAMES,
     Batch, map_batch_create, map_batch_configure, map_batch_step, map_batch_destroy,
 )

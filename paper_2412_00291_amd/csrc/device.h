@@ -849,6 +849,35 @@ __device__ __forceinline__ int label_voxel(const MapView &m, const CameraSet &cs
     return votes;
 }
 
+// Label fusion from a label range image (the scan's points labelled by a point-cloud
+// segmentation): voxel li of the block at bc (slot `slot`) takes the label at its nearest
+// pixel of the scan model under pose T (the pixel rule of the projective update) and votes
+// with the rule of the camera labels.  Returns 1 if it voted.
+__device__ __forceinline__ int label_voxel_lidar(const MapView &m, const LidarLUT &L, const Pose &T,
+                                                 const uint8_t *__restrict__ img, int slot, int3 bc, int li)
+{
+    const float nu = m.nu;
+    const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
+    const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
+    const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
+    const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
+    const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
+    const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
+    int row, col;
+    if (!nearest_pixel(L, px, py, pz, row, col)) return 0;
+    const int l = img[(size_t)row * L.cols + col];
+    if (l >= m.n_classes) return 0;
+    const size_t vi = (size_t)slot * kBlockVoxels + li;
+    uint16_t *cnt = m.counts + (size_t)slot * m.n_classes * kBlockVoxels + li;
+    unsigned c = cnt[(size_t)l * kBlockVoxels];
+    if (c < 65535u) c++;
+    cnt[(size_t)l * kBlockVoxels] = (uint16_t)c;
+    const int fl = m.fused[vi];
+    const unsigned cf = fl == 255 ? 0u : (fl == l ? c : (unsigned)cnt[(size_t)fl * kBlockVoxels]);
+    if (l != fl && (c > cf || (c == cf && l < fl))) m.fused[vi] = (uint8_t)l;
+    return 1;
+}
+
 // ---------------------------------------------------------------------------------
 // marching cubes of one block by one workgroup (see k_mesh.hip)
 // ---------------------------------------------------------------------------------

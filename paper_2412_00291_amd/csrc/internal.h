@@ -263,6 +263,8 @@ hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, i
                              hipStream_t s);
 hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan,
                               MeshReport *report, int schedule, MeshGrid grid, hipStream_t s);
+hipError_t launch_labels_lidar(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                               const uint8_t *img, int grid, hipStream_t s);
 hipError_t launch_range_image(const LidarLUT &lut, const float *pts, int n, float F, float O,
                               unsigned long long *keys, float *depth, float *height, hipStream_t s);
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,

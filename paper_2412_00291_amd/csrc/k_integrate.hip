@@ -230,6 +230,40 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
     }
 }
 
+// label fusion from a label range image under the scan model: a wavefront per touched
+// block, its band voxels compacted
+__global__ __launch_bounds__(kThreads) void k_labels_lidar(MapView m, FrameView f, LidarLUT L, Pose T,
+                                                           const uint8_t *__restrict__ img)
+{
+    __shared__ unsigned long long s_sum[kThreads / 64];
+    const int n = m.ctr->last_touched;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long my_votes = 0;
+    const int first = (int)blockIdx.x * (kThreads / 64) + wave, stride = (int)gridDim.x * (kThreads / 64);
+    for (int e = first; e < n; e += stride) {
+        const int slot = f.tk_slot[e];
+        const int3 bc = unpack_key(f.tk_key[e]);
+        const BandWords b = band_words(f, e);
+#pragma unroll 1
+        for (int t = lane; t < b.pre[8]; t += 64) my_votes += label_voxel_lidar(m, L, T, img, slot, bc, band_select(b, t));
+    }
+    const unsigned long long w = wave_sum_u64(my_votes);
+    if (lane == 0) s_sum[wave] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kThreads / 64; ++i) t += s_sum[i];
+        if (t) spread_add(m.sync->votes, t);
+    }
+}
+
+hipError_t launch_labels_lidar(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                               const uint8_t *img, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_labels_lidar, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, img);
+    return hipGetLastError();
+}
+
 hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int schedule, int grid,
                          hipStream_t s)
 {

@@ -478,6 +478,29 @@ extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_mode
     return MAP_OK;
 }
 
+extern "C" int map_integrate_labels_lidar(map_t *m, const lidar_model *L, const uint8_t *labels_dev,
+                                          const float T_wl[16], void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (!L || !labels_dev || !T_wl || !L->elev_rad)
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: NULL argument");
+    if (L->rows < 2 || L->cols < 8) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: need rows >= 2, cols >= 8");
+    if (!(L->r_max > 0.0f) || !std::isfinite(L->r_max))
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: r_max must be positive and finite");
+    if (!pose_ok(T_wl)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: pose is not a rigid transform");
+    if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels_lidar: no LiDAR frame integrated yet");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    const int rc = ensure_lut(m, L, s);
+    if (rc) return rc;
+    const Pose T = to_pose(T_wl);
+    HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
+        return launch_labels_lidar(m->v, m->f, m->lut, T, labels_dev, grid_for(m->f.tk_cap, 1, 2048), s);
+    }));
+    m->last_stream = s;
+    return MAP_OK;
+}
+
 extern "C" int map_integrate_labels(map_t *m, const camera_model *cam, const uint8_t *labels_dev,
                                     const float T_wc[16], void *stream)
 {

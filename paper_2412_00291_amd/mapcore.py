@@ -72,6 +72,7 @@ _sig = {
     "map_integrate_labels_multi": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P]),
     "map_extract_mesh": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
     "map_query_sdf": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    "map_integrate_labels_lidar": (ctypes.c_int, [_P, ctypes.POINTER(_Lidar), _P, _P, _P]),
     "map_range_image": (ctypes.c_int, [_P, ctypes.POINTER(_Lidar), _P, _I64, ctypes.c_float, ctypes.c_float, _P, _P,
                                        _P]),
     "map_sdf_pose_adjoint": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
@@ -198,6 +199,18 @@ def map_integrate_labels(handle, cam: CameraModel, labels_dev, T_wc, stream=None
     keep, T = _pose(T_wc)
     return _lib.map_integrate_labels(handle, ctypes.byref(cam._c()), _dev(labels_dev, torch.uint8, "labels"), T,
                                      _stream(stream))
+
+
+def map_integrate_labels_lidar(handle, lidar: LidarModel, labels_dev, T_wl, stream=None):
+    """Label range image (uint8 [rows, cols] device tensor, the scan's pixel layout) under
+    the scan pose T_wl: the last scan's band voxels vote with the label at their pixel."""
+    import torch
+    if labels_dev.numel() != lidar.rows * lidar.cols:
+        raise ValueError("label image size does not match the LiDAR model")
+    L = lidar._c()
+    keep, T = _pose(T_wl)
+    return _lib.map_integrate_labels_lidar(handle, ctypes.byref(L), _dev(labels_dev, torch.uint8, "labels"), T,
+                                           _stream(stream))
 
 
 def map_integrate_labels_multi(handle, cams, labels_dev, T_wc, stream=None):
@@ -376,6 +389,9 @@ class Map:
 
     def integrate_labels(self, cam, labels_dev, T_wc, stream=None):
         return self._check(map_integrate_labels(self.h, cam, labels_dev, T_wc, stream))
+
+    def integrate_labels_lidar(self, lidar, labels_dev, T_wl, stream=None):
+        return self._check(map_integrate_labels_lidar(self.h, lidar, labels_dev, T_wl, stream))
 
     def integrate_labels_multi(self, cams, labels_dev, T_wc, stream=None):
         return self._check(map_integrate_labels_multi(self.h, cams, labels_dev, T_wc, stream))
