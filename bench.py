@@ -492,8 +492,8 @@ def main():
         write_traffic(args.write_traffic)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
-              "(maps shard by block ownership, see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU; runs on several GPUs are not implemented "
+              "(a map would shard by block ownership)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -8,7 +8,7 @@ import oracle
 
 
 def step_log(msg):
-    """Append a progress line to gpurun_out/steps.log (names the step before it runs)."""
+    """Append a progress line to the output folder's steps.log (names the step before it runs)."""
     os.makedirs("gpurun_out", exist_ok=True)
     with open(os.path.join("gpurun_out", "steps.log"), "a") as fh:
         fh.write(f"{time.strftime('%H:%M:%S')} {msg}\n")
