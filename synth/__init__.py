@@ -268,7 +268,7 @@ def tiny_scene(seed=1):
     return Scene(objs, ground_kind=1, ground_z=gz, bands=(), ground_default_cls=0, cell=4.0)
 
 
-# cfg2 street classes (19 classes)
+# street scene classes (19 classes)
 ROAD, SIDEWALK, BUILDING, TERRAIN, POLE, TRUNK, VEGETATION = 0, 1, 2, 3, 4, 5, 6
 
 
