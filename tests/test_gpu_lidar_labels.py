@@ -76,3 +76,20 @@ def test_no_scan_is_reported(torch_dev):
     m = Map(w.voxel, w.trunc, w.n_classes, 1 << 12)
     lab = torch.zeros(w.lidar.rows, w.lidar.cols, dtype=torch.uint8, device=dev)
     assert map_integrate_labels_lidar(m.h, lidar_model(w.lidar), lab, np.eye(4, dtype=np.float32)) == MAP_ERR_NO_SCAN
+
+
+def test_invalid_arguments_are_rejected(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import MAP_ERR_INVALID_ARG, map_integrate_labels_lidar
+    w = synth.tiny_workload()
+    m, _ = _pair(w)
+    f = w.frame(0, with_labels=False)
+    lid = lidar_model(w.lidar)
+    m.integrate_lidar(lid, torch.from_numpy(f.range).to(dev), f.T_wl)
+    lab = torch.zeros(w.lidar.rows, w.lidar.cols, dtype=torch.uint8, device=dev)
+    sheared = f.T_wl.copy()
+    sheared[0, 1] += 0.1  # not a rotation
+    assert map_integrate_labels_lidar(m.h, lid, lab, sheared) == MAP_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        map_integrate_labels_lidar(m.h, lid, lab[:3], f.T_wl)
+    assert m.sync() == 0

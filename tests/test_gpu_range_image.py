@@ -122,3 +122,22 @@ def test_depth_only(torch_dev, street):
     oD, _, _ = oracle.range_image(street.lidar.rows, street.lidar.cols, street.lidar.elev_rad,
                                   street.lidar.r_max, pts, F=3.0)
     np.testing.assert_array_equal(D, oD)
+
+
+def test_invalid_arguments_are_rejected_before_any_launch(torch_dev):
+    torch, dev = torch_dev
+    from paper_2412_00291_amd import MAP_ERR_INVALID_ARG, map_range_image
+    from paper_2412_00291_amd.mapcore import LidarModel
+    lidar = synth.uniform_lidar(16, 1800, 15.0, -15.0, 40.0)
+    m = _map()
+    P = torch.zeros(10, 3, dtype=torch.float32, device=dev)
+    D = torch.zeros(16, 1800, dtype=torch.float32, device=dev)
+    good = lidar_model(lidar)
+    assert map_range_image(m.h, good, P, D, None, float("inf"), 0.0) == MAP_ERR_INVALID_ARG
+    assert map_range_image(m.h, good, P, D, None, 1.0, float("nan")) == MAP_ERR_INVALID_ARG
+    no_range = LidarModel(16, 1800, np.ascontiguousarray(lidar.elev_rad, np.float32), 0.0)
+    assert map_range_image(m.h, no_range, P, D, None) == MAP_ERR_INVALID_ARG
+    rising = LidarModel(16, 1800, np.ascontiguousarray(lidar.elev_rad[::-1], np.float32), 40.0)
+    assert map_range_image(m.h, rising, P, D, None) == MAP_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        map_range_image(m.h, good, P, torch.zeros(5, dtype=torch.float32, device=dev), None)
