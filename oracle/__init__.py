@@ -14,22 +14,42 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# Builds of the one source: plain (the parity reference), OpenMP (the same results on
+# several threads, for the CPU timing baseline) and, for the sanitizer tests, plain with
+# AddressSanitizer and UndefinedBehaviorSanitizer.  MAPCORE_ORACLE_LIB names a library to
+# load in place of the plain build (the sanitizer tests set it in a child process).
+VARIANTS = {
+    "plain": ("liboracle.so", []),
+    "omp": ("liboracle_omp.so", ["-fopenmp"]),
+    "san": ("liboracle_san.so", ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                                 "-fno-omit-frame-pointer", "-g"]),
+}
 CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
-_lib = None
+_libs = {}
 
 OK, INVALID, CAPACITY, BUFFER, NO_SCAN = 0, -1, -2, -3, -4
 MESH_DIRTY, MESH_ALL = 0, 1
 
 
-def build(force: bool = False) -> str:
+def lib_path(variant: str = "plain") -> str:
+    return os.path.join(_HERE, VARIANTS[variant][0])
+
+
+def build(force: bool = False, variant: str = "plain") -> str:
     src = os.path.join(_HERE, "oracle.c")
     hdr = os.path.join(_HERE, "oracle.h")
+    out = lib_path(variant)
     newest = max(os.path.getmtime(src), os.path.getmtime(hdr))
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < newest:
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src, "-lm"])
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    if force or not os.path.exists(out) or os.path.getmtime(out) < newest:
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, *VARIANTS[variant][1], "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def build_all(force: bool = False):
+    for v in ("plain", "omp"):
+        build(force, v)
 
 
 class _Stats(ctypes.Structure):
@@ -37,12 +57,15 @@ class _Stats(ctypes.Structure):
                 ("touched", "new_blocks", "updates", "votes", "mesh_blocks", "triangles", "allocated")]
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = ctypes.CDLL(LIB_PATH)
+def _load(variant: str = "plain"):
+    L = _libs.get(variant)
+    if L is None:
+        path = os.environ.get("MAPCORE_ORACLE_LIB") if variant == "plain" else None
+        if not path:
+            path = lib_path(variant)
+            if not os.path.exists(path):
+                build(variant=variant)
+        L = ctypes.CDLL(path)
         P, I, I64, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
         L.om_create.restype = P
         L.om_create.argtypes = [F, F, I, I64]
@@ -68,8 +91,15 @@ def _load():
         L.om_pose_adjoint.argtypes = [P, P, P, I, I64, P, P, P, P]
         L.om_set_block.argtypes = [P, I, I, I, P, P, P]
         L.om_cube_triangles.argtypes = [I, P]
-        _lib = L
-    return _lib
+        L.om_threads.restype = I
+        L.om_threads.argtypes = []
+        _libs[variant] = L
+    return L
+
+
+def threads(variant: str = "plain") -> int:
+    """Threads the given build uses (OpenMP's maximum for the omp build, else 1)."""
+    return int(_load(variant).om_threads())
 
 
 def _p(a):
@@ -124,8 +154,8 @@ def range_image(lidar_rows, lidar_cols, elev, r_max, pts, F=1.0, O=0.0):
 class OracleMap:
     """One map held by the CPU oracle."""
 
-    def __init__(self, voxel, trunc, n_classes, max_blocks=1 << 22):
-        self._L = _load()
+    def __init__(self, voxel, trunc, n_classes, max_blocks=1 << 22, variant="plain"):
+        self._L = _load(variant)
         self.voxel, self.trunc, self.n_classes = float(voxel), float(trunc), int(n_classes)
         self.h = self._L.om_create(voxel, trunc, n_classes, max_blocks)
         if not self.h:

@@ -24,6 +24,11 @@
  * Sign decisions between a point and a pixel boundary are exact (fp64 products of fp32
  * operands).  The block walk is exact integer arithmetic.  The SDF query adjoint is fp64.
  *
+ * Threads: the same source also builds with OpenMP (for the CPU timing baseline only).
+ * Its parallel loops are over independent items (rows of a scan, touched blocks, meshed
+ * blocks), each writing only its own item, with sums as reductions and per-block
+ * outputs concatenated in order, so both builds compute identical results.
+ *
  * Parity status: every function here is pinned by the CPU tests (closed forms, brute
  * force, invariants, textbook equivalences).  Two choices are fixed only by rule and
  * invariants, not by a value the paper prints: the label-visibility reading and the
@@ -35,6 +40,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define BLOCK_VOXELS 512
 #define DOMAIN_VOXELS ((1 << 19) - 64) /* |voxel index| stays below 2^19 */
@@ -50,7 +58,8 @@ typedef struct {
 } oblock;
 
 typedef struct {
-    int64_t *keys; /* 0 = empty; stored key is packed + 1 */
+    uint64_t *keys; /* 0 = empty; stored key is packed + 1 (unsigned: the packed key of
+                       block (-1, -1, -1) is 2^63 - 1) */
     int64_t *vals;
     int64_t cap, n;
 } ohash;
@@ -91,7 +100,7 @@ static void hash_init(ohash *h, int64_t cap)
 {
     h->cap = cap;
     h->n = 0;
-    h->keys = (int64_t *)calloc(cap, sizeof(int64_t));
+    h->keys = (uint64_t *)calloc(cap, sizeof(uint64_t));
     h->vals = (int64_t *)calloc(cap, sizeof(int64_t));
 }
 
@@ -104,7 +113,7 @@ static void hash_free(ohash *h)
 
 static int64_t hash_find(const ohash *h, int64_t key)
 {
-    int64_t stored = key + 1;
+    uint64_t stored = (uint64_t)key + 1u;
     int64_t i = (int64_t)(mix64((uint64_t)key) & (uint64_t)(h->cap - 1));
     for (;;) {
         if (h->keys[i] == 0) return -1;
@@ -120,7 +129,7 @@ static void hash_grow(ohash *h)
     ohash nh;
     hash_init(&nh, h->cap * 2);
     for (int64_t i = 0; i < h->cap; ++i)
-        if (h->keys[i]) hash_put(&nh, h->keys[i] - 1, h->vals[i]);
+        if (h->keys[i]) hash_put(&nh, (int64_t)(h->keys[i] - 1u), h->vals[i]);
     hash_free(h);
     *h = nh;
 }
@@ -128,7 +137,7 @@ static void hash_grow(ohash *h)
 static void hash_put(ohash *h, int64_t key, int64_t val)
 {
     if (2 * (h->n + 1) > h->cap) hash_grow(h);
-    int64_t stored = key + 1;
+    uint64_t stored = (uint64_t)key + 1u;
     int64_t i = (int64_t)(mix64((uint64_t)key) & (uint64_t)(h->cap - 1));
     while (h->keys[i] != 0 && h->keys[i] != stored) i = (i + 1) & (h->cap - 1);
     if (h->keys[i] == 0) h->n++;
@@ -541,13 +550,16 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
     lut t;
     if (!lut_build(&t, rows, cols, elev)) return OM_INVALID;
 
-    /* T_k: every block met by the band segment of a valid return */
-    ohash frame;
-    hash_init(&frame, 1024);
-    int64_t nlist = 0, caplist = 1024;
-    int64_t *list = (int64_t *)malloc(caplist * sizeof(int64_t));
-    int32_t cand[3 * 256];
-    for (int k = 0; k < rows; ++k)
+    /* T_k: every block met by the band segment of a valid return.  Each row's blocks
+     * are listed on their own (rows are independent: the OpenMP build takes them in
+     * parallel), then merged without repeats. */
+    int64_t **rowkeys = (int64_t **)calloc((size_t)rows, sizeof(int64_t *));
+    int64_t *rown = (int64_t *)calloc((size_t)rows, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < rows; ++k) {
+        int32_t cand[3 * 256];
+        int64_t cap = 256, n = 0;
+        int64_t *keys = (int64_t *)malloc(cap * sizeof(int64_t));
         for (int c = 0; c < cols; ++c) {
             float r = range[(size_t)k * cols + c];
             if (!valid_return(r, r_max)) continue;
@@ -556,26 +568,50 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
             int64_t nb = om_segment_blocks(Q0, Q1, cand, 256);
             if (nb > 256) abort(); /* cannot happen for tau <= 64 nu */
             for (int64_t j = 0; j < nb; ++j) {
-                int64_t key = pack_key(cand[3 * j], cand[3 * j + 1], cand[3 * j + 2]);
-                if (hash_find(&frame, key) >= 0) continue;
-                hash_put(&frame, key, nlist);
-                if (nlist == caplist) {
-                    caplist *= 2;
-                    list = (int64_t *)realloc(list, caplist * sizeof(int64_t));
+                if (n == cap) {
+                    cap *= 2;
+                    keys = (int64_t *)realloc(keys, cap * sizeof(int64_t));
                 }
-                list[nlist++] = key;
+                keys[n++] = pack_key(cand[3 * j], cand[3 * j + 1], cand[3 * j + 2]);
             }
         }
+        rowkeys[k] = keys;
+        rown[k] = n;
+    }
+    ohash frame;
+    hash_init(&frame, 1024);
+    int64_t nlist = 0, caplist = 1024;
+    int64_t *list = (int64_t *)malloc(caplist * sizeof(int64_t));
+    for (int k = 0; k < rows; ++k) {
+        for (int64_t j = 0; j < rown[k]; ++j) {
+            int64_t key = rowkeys[k][j];
+            if (hash_find(&frame, key) >= 0) continue;
+            hash_put(&frame, key, nlist);
+            if (nlist == caplist) {
+                caplist *= 2;
+                list = (int64_t *)realloc(list, caplist * sizeof(int64_t));
+            }
+            list[nlist++] = key;
+        }
+        free(rowkeys[k]);
+    }
+    free(rowkeys);
+    free(rown);
     hash_free(&frame);
     /* N_k and the capacity check happen before any block is created */
     int64_t n_new = 0;
     for (int64_t i = 0; i < nlist; ++i)
         if (hash_find(&m->h, list[i]) < 0) n_new++;
     if (m->nblocks + n_new > m->max_blocks) {
-        /* rejected: the map is unchanged and there is no scan to label */
+        /* rejected: the map is unchanged, and the scan it leaves for label calls is
+         * empty (a frame was submitted, so they are no-ops, not NO_SCAN) */
         free(list);
         lut_free(&t);
         m->ntouched = 0;
+        m->has_scan = 1;
+        m->st.touched = 0;
+        m->st.new_blocks = 0;
+        m->st.updates = 0;
         m->st.votes = 0;
         return OM_CAPACITY;
     }
@@ -604,6 +640,8 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
     const float nu = m->nu, tau = m->tau, two_tau = m->tau + m->tau;
     const float tx = T[3], ty = T[7], tz = T[11];
     int64_t updates = 0;
+    /* blocks are independent (one update per voxel per frame) */
+#pragma omp parallel for reduction(+ : updates) schedule(dynamic, 4)
     for (int64_t i = 0; i < m->ntouched; ++i) {
         oblock *b = m->blocks[m->touched[i]];
         memset(b->band, 0, sizeof(b->band));
@@ -688,6 +726,7 @@ int om_integrate_labels(omap *m, int width, int height, float fx, float fy, floa
     const float tx = T[3], ty = T[7], tz = T[11];
     const float fw = (float)width, fh = (float)height;
     int64_t votes = 0;
+#pragma omp parallel for reduction(+ : votes) schedule(dynamic, 4)
     for (int64_t i = 0; i < m->ntouched; ++i) {
         oblock *b = m->blocks[m->touched[i]];
         for (int li = 0; li < BLOCK_VOXELS; ++li) {
@@ -733,6 +772,7 @@ int om_integrate_labels_lidar(omap *m, int rows, int cols, const float *elev, co
     const float nu = m->nu;
     const float tx = T[3], ty = T[7], tz = T[11];
     int64_t votes = 0;
+#pragma omp parallel for reduction(+ : votes) schedule(dynamic, 4)
     for (int64_t i = 0; i < m->ntouched; ++i) {
         oblock *b = m->blocks[m->touched[i]];
         for (int li = 0; li < BLOCK_VOXELS; ++li) {
@@ -906,67 +946,134 @@ static int64_t edge_key(const int64_t a[3], int axis)
     return ((a[0] + off) << 42) | ((a[1] + off) << 22) | ((a[2] + off) << 2) | axis;
 }
 
+/* The triangles of one block's 512 cubes (cube order z, y, x), written to pos, lab and
+ * (if non-NULL) ekey while fewer than cap are written; returns the block's count. */
+static int64_t mesh_block(const omap *m, const oblock *blk, int64_t cap, float *pos, uint8_t *lab, int64_t *ekey)
+{
+    const float nu = m->nu;
+    int64_t ntri = 0;
+    for (int lz = 0; lz < 8; ++lz)
+        for (int ly = 0; ly < 8; ++ly)
+            for (int lx = 0; lx < 8; ++lx) {
+                int64_t base[3] = {8LL * blk->b[0] + lx, 8LL * blk->b[1] + ly, 8LL * blk->b[2] + lz};
+                float Dc[8];
+                uint8_t Fc[8];
+                int ok = 1, mask = 0;
+                for (int n = 0; n < 8 && ok; ++n) {
+                    int64_t v[3] = {base[0] + (n & 1), base[1] + ((n >> 1) & 1), base[2] + ((n >> 2) & 1)};
+                    int li;
+                    oblock *cb = voxel_at(m, v, &li);
+                    if (!cb || !(cb->W[li] > 0.0f)) { ok = 0; break; }
+                    Dc[n] = cb->D[li];
+                    Fc[n] = cb->fused[li];
+                    if (Dc[n] < 0.0f) mask |= 1 << n;
+                }
+                if (!ok || mask == 0 || mask == 255) continue;
+                int tris[12][3];
+                int nt = cube_triangles(mask, tris);
+                for (int q = 0; q < nt; ++q) {
+                    if (ntri < cap) {
+                        for (int k = 0; k < 3; ++k) {
+                            int e = tris[q][k], off[3];
+                            edge_base(e, off);
+                            int ax = e / 4;
+                            int ca = corner_of(off);
+                            int ob[3] = {off[0], off[1], off[2]};
+                            ob[ax] = 1;
+                            int cb = corner_of(ob);
+                            int64_t va[3] = {base[0] + off[0], base[1] + off[1], base[2] + off[2]};
+                            float Da = Dc[ca], Db = Dc[cb];
+                            float tt = Da / (Da - Db);
+                            float *P = pos + 9 * ntri + 3 * k;
+                            for (int j = 0; j < 3; ++j) P[j] = (float)va[j] * nu;
+                            P[ax] = P[ax] + tt * nu;
+                            lab[3 * ntri + k] = fabsf(Da) <= fabsf(Db) ? Fc[ca] : Fc[cb];
+                            if (ekey) ekey[3 * ntri + k] = edge_key(va, ax);
+                        }
+                    }
+                    ntri++;
+                }
+            }
+    return ntri;
+}
+
 int om_extract_mesh(omap *m, int mode, int64_t cap_tris, float *pos, uint8_t *lab, int64_t *ekey,
                     int64_t *n_tris)
 {
     if (!m || !n_tris || cap_tris < 0 || (mode != OM_MESH_DIRTY && mode != OM_MESH_ALL)) return OM_INVALID;
     if (cap_tris > 0 && (!pos || !lab)) return OM_INVALID;
-    const float nu = m->nu;
-    int64_t ntri = 0, nblk = 0;
-    for (int64_t bi = 0; bi < m->nblocks; ++bi) {
-        oblock *blk = m->blocks[bi];
-        if (mode == OM_MESH_DIRTY && !blk->dirty) continue;
-        nblk++;
-        for (int lz = 0; lz < 8; ++lz)
-            for (int ly = 0; ly < 8; ++ly)
-                for (int lx = 0; lx < 8; ++lx) {
-                    int64_t base[3] = {8LL * blk->b[0] + lx, 8LL * blk->b[1] + ly, 8LL * blk->b[2] + lz};
-                    float Dc[8];
-                    uint8_t Fc[8];
-                    int ok = 1, mask = 0;
-                    for (int n = 0; n < 8 && ok; ++n) {
-                        int64_t v[3] = {base[0] + (n & 1), base[1] + ((n >> 1) & 1), base[2] + ((n >> 2) & 1)};
-                        int li;
-                        oblock *cb = voxel_at(m, v, &li);
-                        if (!cb || !(cb->W[li] > 0.0f)) { ok = 0; break; }
-                        Dc[n] = cb->D[li];
-                        Fc[n] = cb->fused[li];
-                        if (Dc[n] < 0.0f) mask |= 1 << n;
-                    }
-                    if (!ok || mask == 0 || mask == 255) continue;
-                    int tris[12][3];
-                    int nt = cube_triangles(mask, tris);
-                    for (int q = 0; q < nt; ++q) {
-                        if (ntri < cap_tris) {
-                            for (int k = 0; k < 3; ++k) {
-                                int e = tris[q][k], off[3];
-                                edge_base(e, off);
-                                int ax = e / 4;
-                                int ca = corner_of(off);
-                                int ob[3] = {off[0], off[1], off[2]};
-                                ob[ax] = 1;
-                                int cb = corner_of(ob);
-                                int64_t va[3] = {base[0] + off[0], base[1] + off[1], base[2] + off[2]};
-                                float Da = Dc[ca], Db = Dc[cb];
-                                float tt = Da / (Da - Db);
-                                float *P = pos + 9 * ntri + 3 * k;
-                                for (int j = 0; j < 3; ++j) P[j] = (float)va[j] * nu;
-                                P[ax] = P[ax] + tt * nu;
-                                lab[3 * ntri + k] = fabsf(Da) <= fabsf(Db) ? Fc[ca] : Fc[cb];
-                                if (ekey) ekey[3 * ntri + k] = edge_key(va, ax);
-                            }
-                        }
-                        ntri++;
-                    }
+    /* the blocks to mesh, in slot order */
+    int64_t nsel = 0;
+    int64_t *sel = (int64_t *)malloc((size_t)(m->nblocks > 0 ? m->nblocks : 1) * sizeof(int64_t));
+    for (int64_t bi = 0; bi < m->nblocks; ++bi)
+        if (mode == OM_MESH_ALL || m->blocks[bi]->dirty) sel[nsel++] = bi;
+    /* Blocks are independent: each is meshed into buffers of its own (in parallel in the
+     * OpenMP build), and the buffers are concatenated in slot order. */
+    const int64_t kMaxBlockTris = 12 * BLOCK_VOXELS; /* at most 12 triangles a cube */
+    int64_t *cnt = (int64_t *)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(int64_t));
+    float **bpos = (float **)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(float *));
+    uint8_t **blab = (uint8_t **)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(uint8_t *));
+    int64_t **bkey = (int64_t **)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(int64_t *));
+#pragma omp parallel
+    {
+        float *sp = (float *)malloc((size_t)kMaxBlockTris * 9 * sizeof(float));
+        uint8_t *sl = (uint8_t *)malloc((size_t)kMaxBlockTris * 3);
+        int64_t *sk = ekey ? (int64_t *)malloc((size_t)kMaxBlockTris * 3 * sizeof(int64_t)) : NULL;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < nsel; ++i) {
+            int64_t n = mesh_block(m, m->blocks[sel[i]], kMaxBlockTris, sp, sl, sk);
+            cnt[i] = n;
+            if (n > 0 && cap_tris > 0) {
+                bpos[i] = (float *)malloc((size_t)n * 9 * sizeof(float));
+                blab[i] = (uint8_t *)malloc((size_t)n * 3);
+                memcpy(bpos[i], sp, (size_t)n * 9 * sizeof(float));
+                memcpy(blab[i], sl, (size_t)n * 3);
+                if (sk) {
+                    bkey[i] = (int64_t *)malloc((size_t)n * 3 * sizeof(int64_t));
+                    memcpy(bkey[i], sk, (size_t)n * 3 * sizeof(int64_t));
                 }
+            }
+        }
+        free(sp);
+        free(sl);
+        free(sk);
     }
+    int64_t ntri = 0;
+    for (int64_t i = 0; i < nsel; ++i) {
+        int64_t k = cnt[i];
+        if (ntri < cap_tris && k > 0) {
+            int64_t c = k < cap_tris - ntri ? k : cap_tris - ntri;
+            memcpy(pos + 9 * ntri, bpos[i], (size_t)c * 9 * sizeof(float));
+            memcpy(lab + 3 * ntri, blab[i], (size_t)c * 3);
+            if (ekey) memcpy(ekey + 3 * ntri, bkey[i], (size_t)c * 3 * sizeof(int64_t));
+        }
+        ntri += k;
+        free(bpos[i]);
+        free(blab[i]);
+        free(bkey[i]);
+    }
+    free(bpos);
+    free(blab);
+    free(bkey);
+    free(cnt);
+    free(sel);
     *n_tris = ntri;
     if (ntri > cap_tris) return OM_BUFFER;
     if (mode == OM_MESH_DIRTY)
         for (int64_t bi = 0; bi < m->nblocks; ++bi) m->blocks[bi]->dirty = 0;
-    m->st.mesh_blocks = nblk;
+    m->st.mesh_blocks = nsel;
     m->st.triangles = ntri;
     return OM_OK;
+}
+
+/* Threads the OpenMP build of this file uses (1 without OpenMP). */
+int om_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -98,6 +98,11 @@ void om_pose_adjoint(const omap *m, const double *xi, const float *pts, int B, i
 int om_set_block(omap *m, int bx, int by, int bz, const float *D, const float *W, const uint8_t *fused);
 int om_cube_triangles(int inside_mask, int *out);
 
+/* Threads this build uses: the library is built twice from this one source, plain
+ * (1 thread) and with OpenMP (loops over rows, touched blocks and meshed blocks run in
+ * parallel; every result is identical, only the time differs). */
+int om_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,23 +27,33 @@ _lib = None
 OBJ_BOX, OBJ_CYL, OBJ_CONE, OBJ_SPHERE = 0, 1, 2, 3
 
 
-def build_lib(force: bool = False) -> str:
-    """Compile the ray caster (host C, OpenMP)."""
+# The sanitizer tests build a second copy with AddressSanitizer and
+# UndefinedBehaviorSanitizer (no OpenMP) and name it in MAPCORE_SYNTH_LIB for a child process.
+SAN_LIB_PATH = os.path.join(_HERE, "libsynth_san.so")
+
+
+def build_lib(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the ray caster (host C, OpenMP; or sanitized and single-threaded)."""
     src = os.path.join(_HERE, "raycast.c")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", tmp, src, "-lm"])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    out = SAN_LIB_PATH if sanitize else _LIB_PATH
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp"
+        extra = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+                 if sanitize else ["-fopenmp"])
+        subprocess.check_call(["gcc", "-O2", *extra, "-fPIC", "-shared", "-std=c11", "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build_lib()
-        lib = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("MAPCORE_SYNTH_LIB")
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(path):
+                build_lib()
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.synth_scene_new.restype = P
         lib.synth_scene_new.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_double,

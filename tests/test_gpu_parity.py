@@ -135,16 +135,27 @@ def test_empty_scan_and_labels(torch_dev):
 
 
 def test_capacity_rejects_frame(torch_dev):
+    """A frame that would exceed max_blocks is rejected whole.  It still counts as a
+    submitted frame: label calls after it return OK and vote nowhere, on both sides (the
+    device reports the rejection at the next synchronising call, the oracle at once)."""
     torch, dev = torch_dev
-    from paper_2412_00291_amd import MAP_ERR_CAPACITY
+    from paper_2412_00291_amd import MAP_ERR_CAPACITY, MAP_OK, map_integrate_labels
     w = synth.tiny_workload()
     f = w.frame(0)
     m, om = _pair(w, max_blocks=100)
-    _step(torch, m, om, w, f)
+    m.integrate_lidar(lidar_model(w.lidar), torch.from_numpy(f.range).to(dev), f.T_wl)
+    assert om.integrate_lidar(w.lidar, f.range, f.T_wl) == oracle.CAPACITY
+    for T, lab, cam in f.cams:
+        g = map_integrate_labels(m.h, camera_model(cam), torch.from_numpy(np.ascontiguousarray(lab)).to(dev), T)
+        o = om.integrate_labels(cam, lab, T)
+        assert g == o == MAP_OK, (g, o)
     assert m.sync() == MAP_ERR_CAPACITY
     assert m.sync() == 0  # the deferred status is reported once
     st, s = m.stats()
+    os_ = om.stats()
     assert s["allocated"] == 0 and s["votes"] == 0 and s["frames"] == 0
+    for k in ("touched", "new_blocks", "updates", "votes", "allocated"):
+        assert s[k] == os_[k] == 0, k
     assert om.num_blocks() == 0
     assert gpu_mesh(m, 0)["n"] == 0
 

@@ -136,10 +136,15 @@ def test_capacity_rejects_frame_and_leaves_map_unchanged():
     T = synth.pose_matrix(np.eye(3), [0.0, 0.0, 0.0])
     rimg = np.full((8, 64), 5.0, np.float32)
     m = oracle.OracleMap(0.2, 0.6, 4, max_blocks=10)
+    cam = synth.Camera(8, 8, 4.0, 4.0, 4.0, 4.0)
+    # labels before any frame was submitted
+    assert m.integrate_labels(cam, np.zeros((8, 8), np.uint8), T) == oracle.NO_SCAN
     assert m.integrate_lidar(lidar, rimg, T) == oracle.CAPACITY
     assert m.num_blocks() == 0
-    assert m.integrate_labels(synth.Camera(8, 8, 4.0, 4.0, 4.0, 4.0), np.zeros((8, 8), np.uint8),
-                              T) == oracle.NO_SCAN
+    # a rejected frame leaves an empty scan: label calls after it vote nowhere and succeed
+    assert m.integrate_labels(cam, np.zeros((8, 8), np.uint8), T) == oracle.OK
+    st = m.stats()
+    assert st["votes"] == 0 and st["touched"] == 0 and m.num_blocks() == 0
 
 
 def test_invalid_arguments():
