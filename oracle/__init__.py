@@ -29,6 +29,28 @@ _libs = {}
 
 OK, INVALID, CAPACITY, BUFFER, NO_SCAN = 0, -1, -2, -3, -4
 MESH_DIRTY, MESH_ALL = 0, 1
+DIST_PROJECTIVE, DIST_NONPROJECTIVE = 0, 1
+DEFAULT_MAX_INCIDENCE = float(np.deg2rad(80.0))  # point filter of the non-projective mode
+
+
+def normal_image(lidar, range_img, T_wl, max_incidence=DEFAULT_MAX_INCIDENCE):
+    """Normal image and point filter of one scan: (kept ranges [R, C], world normals [R, C, 3])."""
+    e = _f32(lidar.elev_rad)
+    r = _f32(range_img)
+    T = _f32(T_wl).reshape(16)
+    kept = np.zeros((lidar.rows, lidar.cols), np.float32)
+    nrm = np.zeros((lidar.rows, lidar.cols, 3), np.float32)
+    st = _load().om_normal_image(lidar.rows, lidar.cols, _p(e), float(lidar.r_max), float(max_incidence),
+                                 _p(r), _p(T), _p(kept), _p(nrm))
+    if st != OK:
+        raise ValueError("invalid scan model")
+    return kept, nrm
+
+
+def nonproj_distance(psi, u, g, n):
+    """Eq. 4 as read here, in fp32 (for pins)."""
+    u, g, n = _f32(u), _f32(g), _f32(n)  # kept alive across the call
+    return float(_load().om_nonproj_distance(float(psi), _p(u), _p(g), _p(n)))
 
 
 def lib_path(variant: str = "plain") -> str:
@@ -93,6 +115,11 @@ def _load(variant: str = "plain"):
         L.om_cube_triangles.argtypes = [I, P]
         L.om_threads.restype = I
         L.om_threads.argtypes = []
+        L.om_set_distance.argtypes = [P, I, F]
+        L.om_normal_image.argtypes = [I, I, P, F, F, P, P, P, P]
+        L.om_nonproj_distance.restype = F
+        L.om_nonproj_distance.argtypes = [F, P, P, P]
+        L.om_block_gradient.argtypes = [P, I, I, I, P]
         _libs[variant] = L
     return L
 
@@ -171,6 +198,16 @@ class OracleMap:
             self.close()
         except Exception:
             pass
+
+    def set_distance(self, mode, max_incidence=None) -> int:
+        """mode DIST_PROJECTIVE or DIST_NONPROJECTIVE; max_incidence in radians."""
+        inc = DEFAULT_MAX_INCIDENCE if max_incidence is None else max_incidence
+        return self._L.om_set_distance(self.h, int(mode), float(inc))
+
+    def block_gradient(self, b):
+        G = np.zeros((3, 512), np.float32)
+        ok = self._L.om_block_gradient(self.h, int(b[0]), int(b[1]), int(b[2]), _p(G))
+        return G if ok else None
 
     def integrate_lidar(self, lidar, range_img, T_wl) -> int:
         e = _f32(lidar.elev_rad)

@@ -54,6 +54,8 @@ typedef struct {
     uint8_t fused[BLOCK_VOXELS];
     uint8_t band[BLOCK_VOXELS];
     uint16_t *counts; /* [L][512] */
+    float *G;         /* [3][512] unit gradient of the non-projective distance (all zero:
+                         none yet); NULL while the map uses the projective distance */
     int dirty;
 } oblock;
 
@@ -76,6 +78,9 @@ struct omap {
     int64_t *touched;
     int64_t ntouched;
     om_stats st;
+    /* distance: 0 projective (Ours-Proj), 1 non-projective (Ours, Eq. 4) */
+    int nonproj;
+    float cos_inc; /* returns whose ray meets their normal at a larger angle are dropped */
 };
 
 /* ------------------------------------------------------------------------------------ */
@@ -195,6 +200,7 @@ void om_destroy(omap *m)
     if (!m) return;
     for (int64_t i = 0; i < m->nblocks; ++i) {
         free(m->blocks[i]->counts);
+        free(m->blocks[i]->G);
         free(m->blocks[i]);
     }
     free(m->blocks);
@@ -214,6 +220,7 @@ static oblock *new_block(omap *m, int32_t x, int32_t y, int32_t z)
     /* initial state: D = 0, W = 0 (unobserved), no votes, fused label unknown (255) */
     memset(b->fused, 255, sizeof(b->fused));
     b->counts = (uint16_t *)calloc((size_t)m->L * BLOCK_VOXELS, sizeof(uint16_t));
+    if (m->nonproj) b->G = (float *)calloc(3 * BLOCK_VOXELS, sizeof(float));
     m->blocks[m->nblocks] = b;
     hash_put(&m->h, pack_key(x, y, z), m->nblocks);
     m->nblocks++;
@@ -497,6 +504,122 @@ int64_t om_segment_blocks(const int64_t *Q0, const int64_t *Q1, int32_t *out, in
 
 static int valid_return(float r, float r_max) { return isfinite(r) && r > 0.0f && r <= r_max; }
 
+/* ------------------------------------------------------------------------------------ */
+/* non-projective distance (Sec. IV-C.2, Eq. 4): normal image, point filter, distance    */
+/* ------------------------------------------------------------------------------------ */
+
+/* Normal image of a scan (Sec. IV-C.2).  Pixel (k, c) back-projects to p = r d(k, c); its
+ * normal is the normalised cross product (p1 - p) x (p2 - p) with p1 from the pixel above
+ * (k - 1, c) and p2 from the pixel to its left (k, c - 1), columns wrapping around (the
+ * scan is a full turn).  Readings: the top row, and pixels whose own or neighbouring
+ * return is invalid, have no normal; the normal is turned to face the sensor.  Point
+ * filter (Sec. V-C): a return is kept only if it has a normal and the angle between its
+ * ray and the normal is at most the incidence limit (cos >= cos_inc).  Outputs: the
+ * filtered range image (0 where dropped) and, for kept returns, the normal rotated into
+ * the world frame by T ([R*C][3], zero elsewhere).  fp32, fixed order. */
+static void normal_image(const lut *t, const float *range, float r_max, float cos_inc, const float *T,
+                         float *rng_out, float *nrm_out)
+{
+    const int R = t->R, C = t->C;
+    for (int k = 0; k < R; ++k)
+        for (int c = 0; c < C; ++c) {
+            const int64_t q = (int64_t)k * C + c;
+            rng_out[q] = 0.0f;
+            nrm_out[3 * q] = nrm_out[3 * q + 1] = nrm_out[3 * q + 2] = 0.0f;
+            const float r = range[q];
+            if (k == 0 || !valid_return(r, r_max)) continue;
+            const int cl = c == 0 ? C - 1 : c - 1;
+            const float r1 = range[q - C], r2 = range[(int64_t)k * C + cl];
+            if (!valid_return(r1, r_max) || !valid_return(r2, r_max)) continue;
+            const float dx = t->ce[k] * t->cp[c], dy = t->ce[k] * t->sp[c], dz = t->se[k];
+            const float px = r * dx, py = r * dy, pz = r * dz;
+            const float p1x = r1 * (t->ce[k - 1] * t->cp[c]), p1y = r1 * (t->ce[k - 1] * t->sp[c]),
+                        p1z = r1 * t->se[k - 1];
+            const float p2x = r2 * (t->ce[k] * t->cp[cl]), p2y = r2 * (t->ce[k] * t->sp[cl]), p2z = r2 * t->se[k];
+            const float ax = p1x - px, ay = p1y - py, az = p1z - pz;
+            const float bx = p2x - px, by = p2y - py, bz = p2z - pz;
+            float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+            const float l2 = (nx * nx + ny * ny) + nz * nz;
+            if (!(l2 > 0.0f) || !isfinite(l2)) continue;
+            const float l = sqrtf(l2);
+            nx = nx / l;
+            ny = ny / l;
+            nz = nz / l;
+            float s = (nx * dx + ny * dy) + nz * dz;  /* cosine of the normal to the ray */
+            if (s > 0.0f) {
+                nx = -nx;
+                ny = -ny;
+                nz = -nz;
+                s = -s;
+            }
+            if (!(-s >= cos_inc)) continue;
+            rng_out[q] = r;
+            for (int i = 0; i < 3; ++i)
+                nrm_out[3 * q + i] = (T[4 * i] * nx + T[4 * i + 1] * ny) + T[4 * i + 2] * nz;
+        }
+}
+
+int om_normal_image(int rows, int cols, const float *elev, float r_max, float max_incidence,
+                    const float *range, const float *T_wl, float *range_out, float *normals_out)
+{
+    lut t;
+    if (!range || !T_wl || !range_out || !normals_out) return OM_INVALID;
+    if (!lut_build(&t, rows, cols, elev)) return OM_INVALID;
+    normal_image(&t, range, r_max, (float)cos((double)max_incidence), T_wl, range_out, normals_out);
+    lut_free(&t);
+    return OM_OK;
+}
+
+/* Eq. 4 as read here.  The printed second case adds |(cos a - 1) sin th / sin a| to
+ * |cos th| psi: a ratio without a length.  For a surface that is locally a circle (Fig.
+ * 3b) through the measured point p with normal n there, and a voxel x = p - psi u on the
+ * ray u whose distance gradient is g, the sine rule in the triangle (centre, p, x) gives
+ * the radius as psi sin th / sin a, so the missing factor is psi and the term is the gap
+ * (cos a - 1) r between that circle and the plane through p normal to g; its sign is
+ * the surface's bend (negative when convex toward the voxel).  With the angles' signs
+ * taken from the vectors, both cases of Eq. 4 collapse into
+ *     d = -psi u.(g + n) / (1 + n.g),
+ * which is |cos th| psi when g = n and the exact distance to a sphere or a cylinder
+ * whatever the bend (the CPU tests pin both).  It needs n.g > -1; where the gradient and
+ * the normal are 90 degrees or more apart (or there is no gradient yet) g is taken to be
+ * n.  fp32 in this order. */
+static float nonproj_distance(float psi, float ux, float uy, float uz, const float g[3], const float n[3])
+{
+    const float hx = g[0] + n[0], hy = g[1] + n[1], hz = g[2] + n[2];
+    const float uh = (ux * hx + uy * hy) + uz * hz;
+    const float ng = (n[0] * g[0] + n[1] * g[1]) + n[2] * g[2];
+    const float f = uh / (1.0f + ng);
+    return -(psi * f);
+}
+
+float om_nonproj_distance(float psi, const float *u, const float *g, const float *n)
+{
+    float ge[3] = {g[0], g[1], g[2]};
+    const float ng = (n[0] * g[0] + n[1] * g[1]) + n[2] * g[2];
+    if (!(ng > 0.0f)) ge[0] = n[0], ge[1] = n[1], ge[2] = n[2];
+    return nonproj_distance(psi, u[0], u[1], u[2], ge, n);
+}
+
+int om_set_distance(omap *m, int mode, float max_incidence)
+{
+    if (!m || (mode != 0 && mode != 1) || !isfinite(max_incidence) || max_incidence < 0.0f) return OM_INVALID;
+    m->nonproj = mode;
+    m->cos_inc = (float)cos((double)max_incidence);
+    if (mode)
+        for (int64_t i = 0; i < m->nblocks; ++i)
+            if (!m->blocks[i]->G) m->blocks[i]->G = (float *)calloc(3 * BLOCK_VOXELS, sizeof(float));
+    return OM_OK;
+}
+
+int om_block_gradient(const omap *m, int bx, int by, int bz, float *G)
+{
+    oblock *b = find_block(m, bx, by, bz);
+    if (!b) return 0;
+    if (b->G) memcpy(G, b->G, 3 * BLOCK_VOXELS * sizeof(float));
+    else memset(G, 0, 3 * BLOCK_VOXELS * sizeof(float));
+    return 1;
+}
+
 /* band segment [max(r - tau, 0), r + tau] of one return in 2^-16 voxel fixed point */
 static void ray_segment(const omap *m, const lut *t, int k, int c, float r, const float *T,
                         int64_t *Q0, int64_t *Q1)
@@ -549,6 +672,15 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
     }
     lut t;
     if (!lut_build(&t, rows, cols, elev)) return OM_INVALID;
+    /* non-projective distance: the normal image and the point filter first; the kept
+     * returns are the scan from here on (allocation and update) */
+    float *nrm = NULL, *kept = NULL;
+    if (m->nonproj) {
+        kept = (float *)malloc((size_t)rows * cols * sizeof(float));
+        nrm = (float *)malloc((size_t)rows * cols * 3 * sizeof(float));
+        normal_image(&t, range, r_max, m->cos_inc, T, kept, nrm);
+        range = kept;
+    }
 
     /* T_k: every block met by the band segment of a valid return.  Each row's blocks
      * are listed on their own (rows are independent: the OpenMP build takes them in
@@ -606,6 +738,8 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
         /* rejected: the map is unchanged, and the scan it leaves for label calls is
          * empty (a frame was submitted, so they are no-ops, not NO_SCAN) */
         free(list);
+        free(kept);
+        free(nrm);
         lut_free(&t);
         m->ntouched = 0;
         m->has_scan = 1;
@@ -668,8 +802,32 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
                     float w = (psi + tau) / two_tau;
                     if (w > 1.0f) w = 1.0f;
                     if (w == 0.0f) continue;
-                    float gam = psi < tau ? psi : tau;
                     float Wo = b->W[li], Do = b->D[li];
+                    float gam;
+                    if (nrm) {
+                        /* Eq. 4 with the normal of the voxel's pixel and the voxel's
+                         * gradient; the ray is the direction from the sensor to the voxel */
+                        const float *n = nrm + 3 * ((size_t)row * cols + col);
+                        float *G = b->G;
+                        const float gs[3] = {G[li], G[BLOCK_VOXELS + li], G[2 * BLOCK_VOXELS + li]};
+                        const float ng = (n[0] * gs[0] + n[1] * gs[1]) + n[2] * gs[2];
+                        const float *ge = ng > 0.0f ? gs : n;
+                        const float ux = dx / dist, uy = dy / dist, uz = dz / dist;
+                        const float d = nonproj_distance(psi, ux, uy, uz, ge, n);
+                        gam = d >= 0.0f ? (d < tau ? d : tau) : (d > -tau ? d : -tau);
+                        /* gradient: the weighted average of the normals, normalised */
+                        const float sx = Wo * gs[0] + w * n[0], sy = Wo * gs[1] + w * n[1],
+                                    sz = Wo * gs[2] + w * n[2];
+                        const float l2 = (sx * sx + sy * sy) + sz * sz;
+                        if (l2 > 0.0f && isfinite(l2)) {
+                            const float l = sqrtf(l2);
+                            G[li] = sx / l;
+                            G[BLOCK_VOXELS + li] = sy / l;
+                            G[2 * BLOCK_VOXELS + li] = sz / l;
+                        }
+                    } else {
+                        gam = psi < tau ? psi : tau;
+                    }
                     float num = Wo * Do + w * gam;
                     float den = Wo + w;
                     b->D[li] = num / den;
@@ -686,6 +844,8 @@ int om_integrate_lidar(omap *m, int rows, int cols, const float *elev, float r_m
             if (n) n->dirty = 1;
         }
     }
+    free(kept);
+    free(nrm);
     lut_free(&t);
     m->has_scan = 1;
     m->st.touched = m->ntouched;

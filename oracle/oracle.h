@@ -98,6 +98,23 @@ void om_pose_adjoint(const omap *m, const double *xi, const float *pts, int B, i
 int om_set_block(omap *m, int bx, int by, int bz, const float *D, const float *W, const uint8_t *fused);
 int om_cube_triangles(int inside_mask, int *out);
 
+/* Distance of the TSDF update: mode 0 projective (the default; the paper's Ours-Proj),
+ * mode 1 non-projective (the paper's Ours, Eq. 4): a normal image of each scan, a point
+ * filter that keeps returns with a normal whose ray meets it at an angle of at most
+ * max_incidence (radians), per-voxel unit gradients as the weighted average of normals,
+ * and d = -psi u.(g + n) / (1 + n.g) truncated in place of psi (the weight stays the
+ * linear weight of psi).  Returns OM_OK or OM_INVALID. */
+int om_set_distance(omap *m, int mode, float max_incidence);
+/* Normal image and point filter of one scan (for pins): range_out [rows*cols] holds the
+ * kept returns (0 elsewhere), normals_out [rows*cols][3] their world-frame normals. */
+int om_normal_image(int rows, int cols, const float *elev, float r_max, float max_incidence,
+                    const float *range, const float *T_wl, float *range_out, float *normals_out);
+/* The non-projective distance of Eq. 4 as read here (for pins): psi, ray u, gradient g,
+ * normal n (g replaced by n when n.g <= 0). */
+float om_nonproj_distance(float psi, const float *u, const float *g, const float *n);
+/* A block's gradients [3][512] (zero in projective mode); returns 0 if absent. */
+int om_block_gradient(const omap *m, int bx, int by, int bz, float *G);
+
 /* Threads this build uses: the library is built twice from this one source, plain
  * (1 thread) and with OpenMP (loops over rows, touched blocks and meshed blocks run in
  * parallel; every result is identical, only the time differs). */

@@ -513,3 +513,54 @@ def perturbed_poses(n, seed, rot_sigma=0.05, trans_sigma=0.2):
 def constant_range(lidar: Lidar, r: float) -> np.ndarray:
     """Range image where every return reads r (sensor inside a sphere of radius r)."""
     return np.full((lidar.rows, lidar.cols), r, dtype=np.float32)
+
+
+# ----------------------------------------------------------------------------------------
+# Micro-scenes with exact ties (block edges and corners, pixel boundaries)
+# ----------------------------------------------------------------------------------------
+
+def lidar_from_degrees(elev_deg, cols, r_max) -> Lidar:
+    """Scan model with the given row elevations (degrees, top row first)."""
+    e = np.deg2rad(np.asarray(elev_deg, dtype=np.float64))
+    return Lidar(len(e), int(cols), e.astype(np.float32), float(r_max))
+
+
+def lattice_ranges(lidar: Lidar, seed: int, step: float, n_max: int, p_drop=0.0) -> np.ndarray:
+    """Range image whose every return is a multiple of `step` in [step, n_max*step]
+    (seeded): with a binary voxel size and a sensor on a block corner, axis-aligned rays
+    then end, or start, exactly on block faces, edges and corners."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = rng.integers(1, n_max + 1, size=(lidar.rows, lidar.cols)).astype(np.float64) * step
+    if p_drop > 0:
+        r[rng.random(r.shape) < p_drop] = 0.0
+    return r.astype(np.float32)
+
+
+def box_room_range(lidar: Lidar, T_wl, lo, hi) -> np.ndarray:
+    """Noiseless range image of a sensor inside the axis-aligned box room [lo, hi]
+    (world frame): each ray's distance to the first wall it meets, in float64, rounded
+    once to float32."""
+    Td = np.asarray(T_wl, dtype=np.float64)
+    o = Td[:3, 3]
+    d = lidar.directions() @ Td[:3, :3].T
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(d > 0, (hi - o) / d, np.where(d < 0, (lo - o) / d, np.inf))
+    r = t.min(axis=1)
+    r[~np.isfinite(r) | (r > lidar.r_max)] = 0.0
+    return r.astype(np.float32).reshape(lidar.rows, lidar.cols)
+
+
+def plane_range(lidar: Lidar, T_wl, normal, offset) -> np.ndarray:
+    """Noiseless range image of the plane {x : normal . x = offset} (world frame): each
+    ray's distance to it in float64 (rays that miss it, or meet it beyond r_max, read 0),
+    rounded once to float32."""
+    Td = np.asarray(T_wl, dtype=np.float64)
+    o = Td[:3, 3]
+    d = lidar.directions() @ Td[:3, :3].T
+    n = np.asarray(normal, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = (float(offset) - n @ o) / (d @ n)
+    t[~np.isfinite(t) | (t <= 0) | (t > lidar.r_max)] = 0.0
+    return t.astype(np.float32).reshape(lidar.rows, lidar.cols)
