@@ -30,6 +30,7 @@ _libs = {}
 OK, INVALID, CAPACITY, BUFFER, NO_SCAN = 0, -1, -2, -3, -4
 MESH_DIRTY, MESH_ALL = 0, 1
 DIST_PROJECTIVE, DIST_NONPROJECTIVE = 0, 1
+LABELS_COUNTS, LABELS_LATEST, LABELS_BAYES = 0, 1, 2
 DEFAULT_MAX_INCIDENCE = float(np.deg2rad(80.0))  # point filter of the non-projective mode
 
 
@@ -120,6 +121,9 @@ def _load(variant: str = "plain"):
         L.om_nonproj_distance.restype = F
         L.om_nonproj_distance.argtypes = [F, P, P, P]
         L.om_block_gradient.argtypes = [P, I, I, I, P]
+        L.om_set_label_fusion.argtypes = [P, I]
+        L.om_integrate_logprobs.argtypes = [P, I, I, F, F, F, F, P, P]
+        L.om_block_logpost.argtypes = [P, I, I, I, P]
         _libs[variant] = L
     return L
 
@@ -203,6 +207,22 @@ class OracleMap:
         """mode DIST_PROJECTIVE or DIST_NONPROJECTIVE; max_incidence in radians."""
         inc = DEFAULT_MAX_INCIDENCE if max_incidence is None else max_incidence
         return self._L.om_set_distance(self.h, int(mode), float(inc))
+
+    def set_label_fusion(self, mode) -> int:
+        return self._L.om_set_label_fusion(self.h, int(mode))
+
+    def integrate_logprobs(self, cam, logp, T_wc) -> int:
+        """logp: float32 [H, W, L] per-pixel class log-probabilities."""
+        lp = _f32(logp)
+        assert lp.shape == (cam.height, cam.width, self.n_classes)
+        T = _f32(T_wc).reshape(16)
+        return self._L.om_integrate_logprobs(self.h, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
+                                             _p(lp), _p(T))
+
+    def block_logpost(self, b):
+        LP = np.zeros((self.n_classes, 512), np.float32)
+        ok = self._L.om_block_logpost(self.h, int(b[0]), int(b[1]), int(b[2]), _p(LP))
+        return LP if ok else None
 
     def block_gradient(self, b):
         G = np.zeros((3, 512), np.float32)

@@ -56,6 +56,8 @@ typedef struct {
     uint16_t *counts; /* [L][512] */
     float *G;         /* [3][512] unit gradient of the non-projective distance (all zero:
                          none yet); NULL while the map uses the projective distance */
+    float *LP;        /* [L][512] log-posterior of each class relative to the most probable
+                         one (Bayes label fusion); NULL in the other label modes */
     int dirty;
 } oblock;
 
@@ -81,6 +83,9 @@ struct omap {
     /* distance: 0 projective (Ours-Proj), 1 non-projective (Ours, Eq. 4) */
     int nonproj;
     float cos_inc; /* returns whose ray meets their normal at a larger angle are dropped */
+    /* label fusion: 0 vote counts (hard labels, Eq. 6 with a symmetric likelihood),
+     * 1 latest label wins (the paper's Ours-wo-Bay), 2 Eq. 6 on log-probability images */
+    int label_mode;
 };
 
 /* ------------------------------------------------------------------------------------ */
@@ -201,6 +206,7 @@ void om_destroy(omap *m)
     for (int64_t i = 0; i < m->nblocks; ++i) {
         free(m->blocks[i]->counts);
         free(m->blocks[i]->G);
+        free(m->blocks[i]->LP);
         free(m->blocks[i]);
     }
     free(m->blocks);
@@ -221,6 +227,7 @@ static oblock *new_block(omap *m, int32_t x, int32_t y, int32_t z)
     memset(b->fused, 255, sizeof(b->fused));
     b->counts = (uint16_t *)calloc((size_t)m->L * BLOCK_VOXELS, sizeof(uint16_t));
     if (m->nonproj) b->G = (float *)calloc(3 * BLOCK_VOXELS, sizeof(float));
+    if (m->label_mode == 2) b->LP = (float *)calloc((size_t)m->L * BLOCK_VOXELS, sizeof(float));
     m->blocks[m->nblocks] = b;
     hash_put(&m->h, pack_key(x, y, z), m->nblocks);
     m->nblocks++;
@@ -874,17 +881,108 @@ static void vote(oblock *b, int li, int l)
     if (l != f && (c > cf || (c == cf && l < f))) b->fused[li] = (uint8_t)l;
 }
 
+/* The label of a voxel's latest observation (the paper's Ours-wo-Bay, Sec. V-C). */
+static void vote_latest(oblock *b, int li, int l) { b->fused[li] = (uint8_t)l; }
+
+int om_set_label_fusion(omap *m, int mode)
+{
+    if (!m || mode < 0 || mode > 2) return OM_INVALID;
+    m->label_mode = mode;
+    if (mode == 2)
+        for (int64_t i = 0; i < m->nblocks; ++i)
+            if (!m->blocks[i]->LP) m->blocks[i]->LP = (float *)calloc((size_t)m->L * BLOCK_VOXELS, sizeof(float));
+    return OM_OK;
+}
+
+/* Visible voxels of the last scan for a pinhole camera (readings of the label update):
+ * band voxels with W > 0 in front of the camera, the pixel the floor of the projection.
+ * Returns the pixel index or -1. */
+static int64_t camera_pixel(const omap *m, const oblock *b, int li, int width, int height, float fx, float fy,
+                            float cx, float cy, const float *T)
+{
+    if (!b->band[li] || !(b->W[li] > 0.0f)) return -1;
+    const float nu = m->nu;
+    int lx = li & 7, ly = (li >> 3) & 7, lz = li >> 6;
+    float x = (float)(8 * b->b[0] + lx) * nu;
+    float y = (float)(8 * b->b[1] + ly) * nu;
+    float z = (float)(8 * b->b[2] + lz) * nu;
+    float dx = x - T[3], dy = y - T[7], dz = z - T[11];
+    float px = (T[0] * dx + T[4] * dy) + T[8] * dz;
+    float py = (T[1] * dx + T[5] * dy) + T[9] * dz;
+    float pz = (T[2] * dx + T[6] * dy) + T[10] * dz;
+    if (!(pz > 0.0f)) return -1;
+    float u = fx * (px / pz) + cx;
+    float v = fy * (py / pz) + cy;
+    if (!(u >= 0.0f && u < (float)width && v >= 0.0f && v < (float)height)) return -1;
+    return (int64_t)(int)v * width + (int)u; /* floor of non-negative values */
+}
+
+/* Eq. 6 taken literally: the recursive Bayes update of each visible voxel's class
+ * distribution by the camera's per-pixel class probabilities, given as log-probabilities
+ * logp [height][width][L] (a segmentation network's log-softmax output).  In log space
+ * the update is an addition per class; the normaliser Z of Eq. 6 is applied by
+ * subtracting the largest log-posterior (so the most probable class holds 0 and the others
+ * their log-ratio to it), which leaves the posterior's ratios, its argmax and every later
+ * update as Z would, with no transcendental function.  The most probable label is the
+ * argmax, ties to the lowest class id.  fp32, classes in increasing order. */
+int om_integrate_logprobs(omap *m, int width, int height, float fx, float fy, float cx, float cy,
+                          const float *logp, const float *T)
+{
+    if (!m || !logp || !T || width < 1 || height < 1) return OM_INVALID;
+    if (!isfinite(fx) || !isfinite(fy) || !isfinite(cx) || !isfinite(cy) || fx == 0.0f || fy == 0.0f)
+        return OM_INVALID;
+    if (!check_pose(T) || m->label_mode != 2) return OM_INVALID;
+    if (!m->has_scan) return OM_NO_SCAN;
+    const int L = m->L;
+    int64_t votes = 0;
+#pragma omp parallel for reduction(+ : votes) schedule(dynamic, 4)
+    for (int64_t i = 0; i < m->ntouched; ++i) {
+        oblock *b = m->blocks[m->touched[i]];
+        for (int li = 0; li < BLOCK_VOXELS; ++li) {
+            const int64_t q = camera_pixel(m, b, li, width, height, fx, fy, cx, cy, T);
+            if (q < 0) continue;
+            const float *o = logp + (size_t)q * L;
+            float mx = -INFINITY;
+            for (int l = 0; l < L; ++l) {
+                const float v = b->LP[(size_t)l * BLOCK_VOXELS + li] + o[l];
+                b->LP[(size_t)l * BLOCK_VOXELS + li] = v;
+                if (v > mx) mx = v;
+            }
+            int best = -1;
+            for (int l = 0; l < L; ++l) {
+                const float v = b->LP[(size_t)l * BLOCK_VOXELS + li] - mx;
+                b->LP[(size_t)l * BLOCK_VOXELS + li] = v;
+                if (best < 0 && v == 0.0f) best = l;
+            }
+            b->fused[li] = (uint8_t)best;
+            votes++;
+        }
+    }
+    m->st.votes += votes;
+    return OM_OK;
+}
+
+int om_block_logpost(const omap *m, int bx, int by, int bz, float *LP)
+{
+    oblock *b = find_block(m, bx, by, bz);
+    if (!b) return 0;
+    if (b->LP) memcpy(LP, b->LP, (size_t)m->L * BLOCK_VOXELS * sizeof(float));
+    else memset(LP, 0, (size_t)m->L * BLOCK_VOXELS * sizeof(float));
+    return 1;
+}
+
 int om_integrate_labels(omap *m, int width, int height, float fx, float fy, float cx, float cy,
                         const uint8_t *labels, const float *T)
 {
     if (!m || !labels || !T || width < 1 || height < 1) return OM_INVALID;
     if (!isfinite(fx) || !isfinite(fy) || !isfinite(cx) || !isfinite(cy) || fx == 0.0f || fy == 0.0f)
         return OM_INVALID;
-    if (!check_pose(T)) return OM_INVALID;
+    if (!check_pose(T) || m->label_mode == 2) return OM_INVALID;
     if (!m->has_scan) return OM_NO_SCAN;
     const float nu = m->nu;
     const float tx = T[3], ty = T[7], tz = T[11];
     const float fw = (float)width, fh = (float)height;
+    const int latest = m->label_mode == 1;
     int64_t votes = 0;
 #pragma omp parallel for reduction(+ : votes) schedule(dynamic, 4)
     for (int64_t i = 0; i < m->ntouched; ++i) {
@@ -906,7 +1004,8 @@ int om_integrate_labels(omap *m, int width, int height, float fx, float fy, floa
             int iu = (int)u, iv = (int)v; /* floor of a non-negative value */
             int l = labels[(size_t)iv * width + iu];
             if (l >= m->L) continue;
-            vote(b, li, l);
+            if (latest) vote_latest(b, li, l);
+            else vote(b, li, l);
             votes++;
         }
     }
@@ -922,7 +1021,7 @@ int om_integrate_labels_lidar(omap *m, int rows, int cols, const float *elev, co
                               const float *T)
 {
     if (!m || !labels || !T || !elev) return OM_INVALID;
-    if (!check_pose(T)) return OM_INVALID;
+    if (!check_pose(T) || m->label_mode == 2) return OM_INVALID;
     lut t;
     if (!lut_build(&t, rows, cols, elev)) return OM_INVALID;
     if (!m->has_scan) {
@@ -949,7 +1048,8 @@ int om_integrate_labels_lidar(omap *m, int rows, int cols, const float *elev, co
             if (!pixel_of(&t, px, py, pz, &row, &col)) continue;
             int l = labels[(size_t)row * cols + col];
             if (l >= m->L) continue;
-            vote(b, li, l);
+            if (m->label_mode == 1) vote_latest(b, li, l);
+            else vote(b, li, l);
             votes++;
         }
     }

@@ -115,6 +115,21 @@ float om_nonproj_distance(float psi, const float *u, const float *g, const float
 /* A block's gradients [3][512] (zero in projective mode); returns 0 if absent. */
 int om_block_gradient(const omap *m, int bx, int by, int bz, float *G);
 
+/* Label fusion mode: 0 vote counts (the default; hard labels, Eq. 6 with a symmetric
+ * likelihood), 1 latest label wins (the paper's Ours-wo-Bay: a visible voxel takes the
+ * label of its latest observation; counts are untouched), 2 Eq. 6 on log-probability
+ * images (om_integrate_logprobs; hard-label calls are then OM_INVALID).  Mode 2 keeps L
+ * fp32 log-posteriors per voxel. */
+int om_set_label_fusion(omap *m, int mode);
+/* Eq. 6 with a camera's per-pixel class log-probabilities logp [height][width][L] (fp32):
+ * each visible voxel of the last scan adds its pixel's log-probabilities to its
+ * log-posterior and subtracts the largest (the normaliser); the most probable label is
+ * the argmax, ties to the lowest class.  Returns OM_OK, OM_INVALID, OM_NO_SCAN. */
+int om_integrate_logprobs(omap *m, int width, int height, float fx, float fy, float cx, float cy,
+                          const float *logp, const float *T_wc);
+/* A block's log-posteriors [L][512] (zero outside mode 2); returns 0 if absent. */
+int om_block_logpost(const omap *m, int bx, int by, int bz, float *LP);
+
 /* Threads this build uses: the library is built twice from this one source, plain
  * (1 thread) and with OpenMP (loops over rows, touched blocks and meshed blocks run in
  * parallel; every result is identical, only the time differs). */

@@ -564,3 +564,34 @@ def plane_range(lidar: Lidar, T_wl, normal, offset) -> np.ndarray:
         t = (float(offset) - n @ o) / (d @ n)
     t[~np.isfinite(t) | (t <= 0) | (t > lidar.r_max)] = 0.0
     return t.astype(np.float32).reshape(lidar.rows, lidar.cols)
+
+
+def logprob_image(labels: np.ndarray, n_classes: int, seed: int, boost: float = 3.0, sigma: float = 1.0):
+    """Per-pixel class log-probabilities [H, W, L] float32, as a segmentation network's
+    log-softmax output: logits N(0, sigma) per class plus `boost` on the pixel's label
+    (none where the label is 255 or >= L), normalised in float64, rounded once."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H, W = labels.shape
+    z = rng.normal(0.0, sigma, size=(H, W, n_classes))
+    lab = labels.astype(np.int64)
+    ok = lab < n_classes
+    ii, jj = np.nonzero(ok)
+    z[ii, jj, lab[ok]] += boost
+    zmax = z.max(axis=2, keepdims=True)
+    lse = zmax + np.log(np.exp(z - zmax).sum(axis=2, keepdims=True))
+    return (z - lse).astype(np.float32)
+
+
+def hard_logprob_image(labels: np.ndarray, n_classes: int, p: float) -> np.ndarray:
+    """Log-probabilities of a hard label with a symmetric likelihood: log p for the
+    pixel's label and log((1 - p) / (L - 1)) for the others (uniform where the label is
+    255 or >= L), float32 [H, W, L]."""
+    H, W = labels.shape
+    lo, hi = np.float32(np.log((1.0 - p) / (n_classes - 1))), np.float32(np.log(p))
+    out = np.full((H, W, n_classes), lo, np.float32)
+    lab = labels.astype(np.int64)
+    ok = lab < n_classes
+    ii, jj = np.nonzero(ok)
+    out[ii, jj, lab[ok]] = hi
+    out[~ok] = np.float32(-np.log(n_classes))
+    return out
