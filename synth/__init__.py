@@ -595,3 +595,22 @@ def hard_logprob_image(labels: np.ndarray, n_classes: int, p: float) -> np.ndarr
     out[ii, jj, lab[ok]] = hi
     out[~ok] = np.float32(-np.log(n_classes))
     return out
+
+
+def ground_truth_cloud(w: Workload, frames, lidar: Lidar = None):
+    """Ground-truth point cloud of a sequence, as the paper's datasets build theirs
+    (labelled scans accumulated with their true poses): the noiseless first hits of every
+    ray of the given frames (within r_max) in the world frame, float32 [n, 3], with the hit
+    object's class, uint8 [n]."""
+    lidar = lidar or w.lidar
+    pts, cls = [], []
+    d0 = lidar.directions()
+    for k in frames:
+        Td = w.poses[k].astype(np.float64)
+        o = Td[:3, 3]
+        d = d0 @ Td[:3, :3].T
+        t, c = w.scene.cast(o, d, lidar.r_max)
+        hit = np.isfinite(t) & (t <= lidar.r_max)
+        pts.append(o + t[hit, None] * d[hit])
+        cls.append(c[hit])
+    return np.concatenate(pts).astype(np.float32), np.concatenate(cls).astype(np.uint8)
