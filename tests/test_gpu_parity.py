@@ -105,14 +105,23 @@ def test_street_window(torch_dev):
 
 
 def test_full_size_128_beam_frame(torch_dev):
-    """One 128x2048 frame (largest LiDAR image), two 1920x1080 label images."""
+    """Two 128x2048 campus frames (largest LiDAR image), two 1920x1080 label images each:
+    state, counters and the dirty mesh after each frame."""
     torch, dev = torch_dev
-    w = synth.campus_workload(n_frames=1)
+    w = synth.campus_workload(n_frames=2)
     w.max_blocks = 1 << 18
     m, om = _pair(w)
-    f = w.frame(0)
-    _step(torch, m, om, w, f)
-    compare_state(m, om)
+    for k in range(2):
+        _step(torch, m, om, w, w.frame(k))
+        rep = compare_state(m, om)
+        gm = gpu_mesh(m, 0)
+        st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_DIRTY)
+        mr = compare_mesh(gm, (pos, lab, keys), voxel=w.voxel)
+        st_, s = m.stats()
+        o = om.stats()
+        for key in ("touched", "new_blocks", "updates", "votes", "allocated", "mesh_blocks", "triangles"):
+            assert s[key] == o[key], (k, key, s[key], o[key])
+    assert rep["blocks"] > 5000 and mr["triangles"] > 100000
 
 
 def test_empty_scan_and_labels(torch_dev):
@@ -316,8 +325,9 @@ def test_query_parity(torch_dev):
 
 
 def test_pose_adjoint_full_size(torch_dev):
-    """64 poses x 131072 points (the differentiation workload) on the GPU; 4 poses checked
-    against the fp64 oracle and fp64 central differences of the oracle loss."""
+    """64 poses x 131072 points (the differentiation workload) on the GPU: every pose's
+    loss and dL/dxi against the fp64 oracle, the point gradients of 4 poses, and fp64
+    central differences of the oracle loss for 2 poses."""
     torch, dev = torch_dev
     w = synth.tiny_workload()
     m, om = _pair(w)
@@ -337,14 +347,18 @@ def test_pose_adjoint_full_size(torch_dev):
     m.sdf_pose_adjoint(X, P, loss2, gxi2, None)
     assert torch.equal(loss, loss2) and torch.equal(gxi, gxi2)  # fixed-order reduction
     L, G, GP = loss.cpu().numpy(), gxi.cpu().numpy(), gp.cpu().numpy()
-    for b in (0, 17, 40, 63):
-        ol, og, ogp, margin = om.pose_adjoint(xi[b:b + 1].astype(np.float64), pts[None])
-        g_norm = np.linalg.norm(ogp[0], axis=1)
+    # every pose: loss and dL/dxi against the fp64 oracle
+    OL, OG, OGP, MARGIN = om.pose_adjoint(xi.astype(np.float64), np.broadcast_to(pts, (B, N, 3)))
+    for b in range(B):
+        g_norm = np.linalg.norm(OGP[b], axis=1)
         scale_t = g_norm.sum()
         scale_w = (np.linalg.norm(pts, axis=1) * g_norm).sum()
-        assert abs(L[b] - ol[0]) <= 1e-4 * ol[0] + 1e-3 * w.trunc ** 2, (b, L[b], ol[0])
-        assert np.all(np.abs(G[b, :3] - og[0, :3]) <= 1e-4 * scale_t + 1e-3), (b, G[b], og[0])
-        assert np.all(np.abs(G[b, 3:] - og[0, 3:]) <= 1e-4 * scale_w + 1e-3), (b, G[b], og[0])
+        assert abs(L[b] - OL[b]) <= 1e-4 * OL[b] + 1e-3 * w.trunc ** 2, (b, L[b], OL[b])
+        assert np.all(np.abs(G[b, :3] - OG[b, :3]) <= 1e-4 * scale_t + 1e-3), (b, G[b], OG[b])
+        assert np.all(np.abs(G[b, 3:] - OG[b, 3:]) <= 1e-4 * scale_w + 1e-3), (b, G[b], OG[b])
+    for b in (0, 17, 40, 63):
+        ogp, margin = OGP[b:b + 1], MARGIN[b:b + 1]
+        g_norm = np.linalg.norm(ogp[0], axis=1)
         # per point: away from cell faces (where the fp32 and fp64 cell choice can differ
         # and the trilinear gradient jumps) the error is bounded relative to the term's
         # natural scale 2 tau |grad D| + |g| (D itself is near zero at the surface)
