@@ -313,6 +313,142 @@ def bench_lidar_labels(torch, frames=24):
                          "unit": "GB/s", "frac": bytes_ / (k_ms * 1e-3) / PEAK_HBM}}
 
 
+def bench_nonprojective(torch, frames=24, warm=4):
+    """The paper's own distance (non-projective, Eq. 4): street frames (64x2048 scan, four
+    1280x720 label cameras, dirty meshing every frame) into a map in that mode; ms per
+    frame over the last frames, and the allocation + TSDF kernels (normal image, point
+    filter, gradients) timed with events and priced at their algorithmic bytes."""
+    import synth
+    from paper_2412_00291_amd import (CameraModel, KERNEL_NAMES, LidarModel, Map, MAP_DIST_NONPROJECTIVE,
+                                      MAP_MESH_DIRTY)
+    w = synth.street_workload(n_frames=frames)
+    lid = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
+    cams = [CameraModel(c.width, c.height, c.fx, c.fy, c.cx, c.cy) for c in w.cameras]
+    dev = []
+    for k in range(frames):
+        f = w.frame(k)
+        dev.append((torch.from_numpy(f.range).cuda(),
+                    [torch.from_numpy(np.ascontiguousarray(l)).cuda() for _, l, _ in f.cams], f.T_wl,
+                    [T for T, _, _ in f.cams]))
+    cap = 4_000_000
+    pos = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
+    lab = torch.empty((cap, 3), dtype=torch.uint8, device="cuda")
+    m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    m.set_distance(MAP_DIST_NONPROJECTIVE, float(np.deg2rad(80.0)))
+    times, stats = [], []
+    mask = (1 << KERNEL_NAMES.index("alloc")) | (1 << KERNEL_NAMES.index("tsdf"))
+    for k, (r, labs, T, Tcs) in enumerate(dev):
+        if k == warm:
+            torch.cuda.synchronize()
+            m.profile_read()
+        timed_frame = k >= warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.integrate_lidar(lid, r, T)
+        m.integrate_labels_multi(cams, labs, Tcs)
+        m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+        torch.cuda.synchronize()
+        if timed_frame:
+            times.append(time.perf_counter() - t0)
+            stats.append(m.stats()[1])
+    # kernel events on a second pass over the same frames (a fresh map)
+    m.close()
+    m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    m.set_distance(MAP_DIST_NONPROJECTIVE, float(np.deg2rad(80.0)))
+    for k, (r, labs, T, Tcs) in enumerate(dev):
+        if k == warm:
+            torch.cuda.synchronize()
+            m.profile(mask)
+        m.integrate_lidar(lid, r, T)
+        m.integrate_labels_multi(cams, labs, Tcs)
+        m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+    prof = m.profile_read()
+    m.close()
+    R, C = w.lidar.rows, w.lidar.cols
+    n = len(stats)
+    U = sum(s["updates"] for s in stats)
+    Tk = sum(s["touched"] for s in stats)
+    # alloc: range + its two neighbours' rows through the caches (4 B), normal image write
+    # (16 B), probe + list per touched block; TSDF: (D, W) and the gradient read and
+    # written per update, the normal image read, the touched list
+    alloc_b = n * (4 * R * C + 16 * R * C) + 16 * Tk
+    tsdf_b = 16 * U + 24 * U + n * 16 * R * C + 16 * Tk
+    out = {"workload": "street-64x2048-v0.1, non-projective distance (Eq. 4), 80 deg point filter, 4 cameras",
+           "frames_timed": n, "ms_per_frame_p50": float(np.median(times) * 1e3),
+           "ms_per_frame_p90": float(np.percentile(times, 90) * 1e3),
+           "voxel_updates_per_s": U / sum(times), "updates_per_frame": U / n}
+    for name, b in (("alloc", alloc_b), ("tsdf", tsdf_b)):
+        ms, launches = prof[name]
+        out[f"{name}_avg_us"] = 1e3 * ms / max(launches, 1)
+        out[f"{name}_roofline"] = {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                                   "unit": "GB/s", "frac": b / (ms * 1e-3) / PEAK_HBM}
+    return out
+
+
+def bench_label_modes(torch, frames=12, warm=2):
+    """Label fusion modes on street frames: the latest label (four 1280x720 label images
+    per frame) and Eq. 6 on two 1280x720x19 fp32 log-probability images per frame; the
+    label kernels alone are timed with events and priced at their algorithmic bytes."""
+    import synth
+    from paper_2412_00291_amd import (CameraModel, KERNEL_NAMES, LidarModel, Map, MAP_LABELS_BAYES,
+                                      MAP_LABELS_LATEST)
+    w = synth.street_workload(n_frames=frames)
+    lid = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
+    cams = [CameraModel(c.width, c.height, c.fx, c.fy, c.cx, c.cy) for c in w.cameras]
+    hf = [w.frame(k) for k in range(frames)]
+    L = w.n_classes
+    out = {}
+    mask = 1 << KERNEL_NAMES.index("labels")
+    # latest label wins
+    m = Map(w.voxel, w.trunc, L, w.max_blocks)
+    m.set_label_fusion(MAP_LABELS_LATEST)
+    dev = [(torch.from_numpy(f.range).cuda(), [torch.from_numpy(np.ascontiguousarray(l)).cuda() for _, l, _ in f.cams],
+            f.T_wl, [T for T, _, _ in f.cams]) for f in hf]
+    votes = 0
+    for k, (r, labs, T, Tcs) in enumerate(dev):
+        if k == warm:
+            torch.cuda.synchronize()
+            m.profile(mask)
+        m.integrate_lidar(lid, r, T)
+        m.integrate_labels_multi(cams, labs, Tcs)
+        if k >= warm:
+            votes += m.stats()[1]["votes"]
+    ms, launches = m.profile_read()["labels"]
+    m.close()
+    b = 2 * votes + launches * sum(c.width * c.height for c in cams)  # fused read + write per vote, images
+    out["latest"] = {"workload": "street-64x2048-v0.1, 4 x 1280x720 label images, latest label wins",
+                     "launches": launches, "kernel_us": 1e3 * ms / max(launches, 1),
+                     "votes_per_s": votes / (ms * 1e-3),
+                     "roofline": {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                                  "unit": "GB/s", "frac": b / (ms * 1e-3) / PEAK_HBM}}
+    del dev
+    # Eq. 6 on log-probability images: two cameras (front, back), a 1 M-block map
+    m = Map(w.voxel, w.trunc, L, 1 << 20)
+    m.set_label_fusion(MAP_LABELS_BAYES)
+    hb = hf[:6]
+    lp = [[torch.from_numpy(synth.logprob_image(f.cams[i][1], L, seed=7 * k + i)).cuda() for i in (0, 2)]
+          for k, f in enumerate(hb)]
+    votes = 0
+    for k, f in enumerate(hb):
+        if k == warm:
+            torch.cuda.synchronize()
+            m.profile(mask)
+        m.integrate_lidar(lid, torch.from_numpy(f.range).cuda(), f.T_wl)
+        for j, i in enumerate((0, 2)):
+            m.integrate_logprobs(cams[i], lp[k][j], f.cams[i][0])
+        if k >= warm:
+            votes += m.stats()[1]["votes"]
+    ms, launches = m.profile_read()["labels"]
+    m.close()
+    b = votes * (12 * L + 1)  # log-posteriors read + written, the pixel's vector read, fused write
+    out["bayes"] = {"workload": "street-64x2048-v0.1, 2 x 1280x720x19 fp32 log-probability images, Eq. 6",
+                    "launches": launches, "kernel_us": 1e3 * ms / max(launches, 1),
+                    "votes_per_s": votes / (ms * 1e-3),
+                    "roofline": {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                                 "unit": "GB/s", "frac": b / (ms * 1e-3) / PEAK_HBM}}
+    return out
+
+
 def bench_batched(torch):
     """Batched form: 16 street maps of uneven size (voxel 0.05-0.4 m, 16/32/64 beams,
     1024-2048 columns, 4-8 frames each here, one 1280x720 camera), autotuned schedule,
@@ -424,44 +560,77 @@ def bench_batched(torch):
             "last_frame_updates_sum": U}
 
 
-def bench_campus(torch, n_frames=12, warm=3):
+_CAMPUS = {}
+
+
+def _campus_frame(args):
+    """One campus frame (worker process): (k, range, [label images]) with or without labels."""
+    import synth
+    k, n_frames, with_labels = args
+    w = _CAMPUS.get(n_frames)
+    if w is None:
+        w = _CAMPUS[n_frames] = synth.campus_workload(n_frames=n_frames)
+    f = w.frame(k, with_labels=with_labels)
+    return k, f.range, [np.ascontiguousarray(l) for _, l, _ in f.cams], [T for T, _, _ in f.cams]
+
+
+def bench_campus(torch, warm=300, timed=200, workers=None):
     """Large-scale form: 128x2048 scans and two 1920x1080 cameras on the campus loop, in a
-    map with room for 2M blocks (~50 GB); steady-state ms/frame over a segment."""
+    map with room for 2M blocks (~50 GB).  Frames 0..warm-1 grow the map (scan and dirty
+    meshing; no labels), then frames warm..warm+timed-1 (scan, both label images, dirty
+    meshing) are timed one by one: the steady state once the map has grown, with early and
+    late frames of the window compared (meshing sees only the dirty blocks).  The frames are
+    generated in worker processes before the GPU work and uploaded to HBM first."""
+    import multiprocessing as mp
     import synth
     from paper_2412_00291_amd import CameraModel, LidarModel, Map, MAP_MESH_DIRTY
-    w = synth.campus_workload(n_frames=n_frames)
+    n = warm + timed
+    w = synth.campus_workload(n_frames=n)
     lid = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
     cams = [CameraModel(c.width, c.height, c.fx, c.fy, c.cx, c.cy) for c in w.cameras]
-    dev = []
-    for k in range(n_frames):
-        f = w.frame(k)
-        dev.append((torch.from_numpy(f.range).cuda(),
-                    [torch.from_numpy(np.ascontiguousarray(l)).cuda() for _, l, _ in f.cams],
-                    f.T_wl, [T for T, _, _ in f.cams]))
-    log(f"[bench] campus: {n_frames} frames generated")
+    workers = workers or min(16, len(os.sched_getaffinity(0)))
+    t0 = time.time()
+    frames = {}
+    with mp.get_context("spawn").Pool(workers) as pool:
+        jobs = [(k, n, k >= warm) for k in range(n)]
+        for k, rng, labs, Tcs in pool.imap_unordered(_campus_frame, jobs, chunksize=4):
+            frames[k] = (torch.from_numpy(rng).cuda(), [torch.from_numpy(l).cuda() for l in labs], Tcs)
+            if len(frames) % 100 == 0:
+                log(f"[bench] campus: {len(frames)}/{n} frames generated ({time.time() - t0:.0f} s)")
     torch.cuda.synchronize()
     cap = 4_000_000
     pos = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
     lab = torch.empty((cap, 3), dtype=torch.uint8, device="cuda")
     m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
-    times, U = [], 0
-    for k, (r, labs, T, Tcs) in enumerate(dev):
+    times, U, alloc, mesh_blocks = [], 0, [], []
+    for k in range(n):
+        r, labs, Tcs = frames[k]
+        T = w.poses[k]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         m.integrate_lidar(lid, r, T)
-        m.integrate_labels_multi(cams, labs, Tcs)
+        if k >= warm:
+            m.integrate_labels_multi(cams, labs, Tcs)
         m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
         t1 = time.perf_counter()
         if k >= warm:
             times.append(t1 - t0)
-            U += m.stats()[1]["updates"]
-    st, s = m.stats()
+            st, s = m.stats()
+            U += s["updates"]
+            alloc.append(s["allocated"])
+            mesh_blocks.append(s["mesh_blocks"])
+        if (k + 1) % 100 == 0:
+            log(f"[bench] campus: frame {k + 1}/{n}")
     m.close()
     t = np.array(times) * 1e3
+    q = max(len(t) // 5, 1)
     return {"workload": f"{w.name}, 2 x 1920x1080 cameras, L=20, max_blocks {w.max_blocks}",
+            "frames": f"{warm} frames of growth (scan and meshing), then frames {warm}-{n - 1} timed",
             "frames_timed": len(times), "ms_per_frame_p50": float(np.median(t)),
             "ms_per_frame_p90": float(np.percentile(t, 90)), "voxel_updates_per_s": U / (t.sum() * 1e-3),
-            "allocated_blocks_end": s["allocated"]}
+            "ms_per_frame_first_fifth": float(np.mean(t[:q])), "ms_per_frame_last_fifth": float(np.mean(t[-q:])),
+            "mesh_blocks_per_frame": float(np.mean(mesh_blocks)),
+            "allocated_blocks_start": int(alloc[0]), "allocated_blocks_end": int(alloc[-1])}
 
 
 def calibrate_copy(torch):
@@ -623,6 +792,8 @@ def main():
     if not args.no_extensions:
         result["extensions"] = {"pose_adjoint": bench_adjoint(torch), "range_image": bench_range_image(torch),
                                 "lidar_labels": bench_lidar_labels(torch),
+                                "nonprojective": bench_nonprojective(torch),
+                                "label_modes": bench_label_modes(torch),
                                 "batched": bench_batched(torch),
                                 "large_scale": bench_campus(torch)}
     if not args.no_cpu_baseline:

@@ -150,6 +150,58 @@ int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
 int map_integrate_labels_lidar(map_t *map, const lidar_model *L, const uint8_t *labels_dev,
                                const float T_wl[16], void *stream);
 
+/* Distance of the TSDF update (Sec. IV-C.2).  MAP_DIST_PROJECTIVE (the default): psi
+ * along the ray, the paper's Ours-Proj baseline.  MAP_DIST_NONPROJECTIVE: the paper's own
+ * distance (Eq. 4, "Ours"), with these readings of the paper:
+ *   - each scan's normal image: pixel (k, c) back-projects to p = r d(k, c); its normal is
+ *     the normalised cross product (p1 - p) x (p2 - p) with p1 from the pixel above (k-1, c)
+ *     and p2 from the pixel to its left (k, c-1; columns wrap), turned to face the sensor;
+ *     the top row and pixels next to an invalid return have none;
+ *   - the point filter (Sec. V-C): a return is kept only if it has a normal and its ray
+ *     meets it at no more than max_incidence radians; dropped returns take no part in the
+ *     frame (allocation or update);
+ *   - per-voxel unit gradients g (float [3] per voxel, pool allocated and zeroed by the
+ *     first switch to this mode), the normalised weight-averaged normals of the voxel's
+ *     pixels: g <- (W g + w n) / |W g + w n| at each update;
+ *   - Eq. 4's second case lacks a length (the circle of Fig. 3b's radius, psi sin th / sin a
+ *     by the sine rule); with the angles signed by the surface's bend both cases become
+ *     d = -psi u.(e + n) / (1 + n.e), u the unit ray to the voxel, n its pixel's normal and
+ *     e = g, or n where n.g <= 0 (no gradient yet);
+ *   - Eq. 5 then averages min(max(d, -tau), tau) with the weight w of the projective psi
+ *     (the same visibility, skip and band rules as the projective update).
+ * Applies to later map_integrate_lidar calls; the batched step accepts only projective
+ * maps.  MAP_ERR_INVALID_ARG for another mode or a non-finite or negative max_incidence.
+ * Synchronises the map's last stream when it allocates the gradient pool
+ * (max_blocks * 6 KiB). */
+#define MAP_DIST_PROJECTIVE 0
+#define MAP_DIST_NONPROJECTIVE 1
+int map_set_distance(map_t *map, int32_t mode, float max_incidence);
+
+/* Label fusion (Sec. IV-C.3).  MAP_LABELS_COUNTS (the default): vote counts with the most
+ * probable label (Eq. 6 with hard labels; map_integrate_labels*).  MAP_LABELS_LATEST: a
+ * visible voxel takes the label of its latest observation, counts untouched (the paper's
+ * Ours-wo-Bay ablation, Sec. V-C; the same calls).  MAP_LABELS_BAYES: Eq. 6 on per-pixel
+ * class log-probability images (map_integrate_logprobs only; the hard-label calls then
+ * return MAP_ERR_INVALID_ARG), with L fp32 log-posteriors per voxel (pool of max_blocks *
+ * L * 2 KiB, allocated and zeroed by the first switch to this mode, which synchronises the
+ * map's last stream).  The batched step accepts only MAP_LABELS_COUNTS maps. */
+#define MAP_LABELS_COUNTS 0
+#define MAP_LABELS_LATEST 1
+#define MAP_LABELS_BAYES 2
+int map_set_label_fusion(map_t *map, int32_t mode);
+
+/* Eq. 6 taken literally (Sec. IV-C.3): a camera's per-pixel class log-probabilities
+ * logp_dev (device float [height][width][n_classes], e.g. a segmentation network's
+ * log-softmax) at pose T_wc update every voxel the last accepted LiDAR frame updated with
+ * |psi| <= tau that projects into the image (the visibility and pixel rule of
+ * map_integrate_labels): its log-posteriors gain the pixel's log-probabilities, then the
+ * largest sum is subtracted from all (the normaliser Z; the posterior's ratios, its argmax
+ * and later updates are those Z gives), and its most probable label becomes the class at
+ * 0 (the lowest on ties).  fp32, classes in increasing order.  Requires MAP_LABELS_BAYES
+ * (else MAP_ERR_INVALID_ARG); MAP_ERR_NO_SCAN before any LiDAR frame.  Asynchronous. */
+int map_integrate_logprobs(map_t *map, const camera_model *cam, const float *logp_dev, const float T_wc[16],
+                           void *stream);
+
 /* Measurement preprocessing (Eq. 3): depth image D = F r and height image H = F (z + O)
  * of n sensor-frame points (device float [n][3], undistorted), for the scan model L (the
  * same model map_integrate_lidar takes; D is then a range image it accepts when F = 1).
@@ -260,6 +312,44 @@ int map_read_block(map_t *map, int32_t bx, int32_t by, int32_t bz, float *D, flo
  * [cap][n_classes][512] uint16.  Returns the number of allocated blocks, -1 on error. */
 int64_t map_download(map_t *map, int64_t cap, int32_t *coords, float *D, float *W,
                      uint8_t *fused, uint16_t *counts);
+
+/* Map-quality metrics (Sec. V-C): the vertices of a reconstructed mesh, M (device float
+ * [n_mesh][3] with labels uint8 [n_mesh], 255 = unlabelled), against a ground-truth cloud
+ * G (device float [n_gt][3] with classes uint8 [n_gt]), with cap = 2 voxel_size (computed
+ * in double from the fp32 voxel size) and d(p, X) = min(cap, distance to the nearest point
+ * of X), distances in fp64 from the fp32 coordinates, the nearest point the lowest index
+ * among equidistant ones:
+ *   re = sqrt(mean over M of d(p, G)^2)                             (Eq. 7)
+ *   cd = mean over M of d(p, G) / 2 + mean over G of d(q, M) / 2     (Eq. 8)
+ *   rc = fraction of G with a point of M within cap (completeness)
+ *   every point of G within cap of M is evaluated with the label of its nearest vertex:
+ *   confusion [pred (n_classes = none or unlabelled)][gt], per class IoU = TP / (TP + FP +
+ *   FN) over the classes that occur, miou their mean, acc = correct / evaluated; points of
+ *   G whose class is >= n_classes are not evaluated.
+ * Optional outputs (NULL to skip): d_mesh_dev (device double [n_mesh], d(p, G)), d_gt_dev
+ * (device double [n_gt], d(q, M)), nn_gt_dev (device int64 [n_gt], the nearest vertex of
+ * each covered point, -1 otherwise), confusion_host (host int64 [(n_classes + 1)
+ * n_classes]).  The library allocates its scratch (two cell grids) for the call and frees
+ * it; synchronous.  Coordinates must lie within 2^20 cap of the origin.  Errors:
+ * MAP_ERR_INVALID_ARG, MAP_ERR_DEVICE (text from map_last_error(NULL)). */
+typedef struct {
+    double re, cd, rc, miou, acc;
+    int64_t n_eval; /* ground-truth points evaluated for the semantic scores */
+} map_quality;
+int map_mesh_quality(const float *mesh_pts_dev, const uint8_t *mesh_lab_dev, int64_t n_mesh,
+                     const float *gt_pts_dev, const uint8_t *gt_lab_dev, int64_t n_gt, float voxel_size,
+                     int32_t n_classes, int32_t device, double *d_mesh_dev, double *d_gt_dev, int64_t *nn_gt_dev,
+                     int64_t *confusion_host, map_quality *out, void *stream);
+
+/* Test access (synchronous): the per-voxel gradients [cap][3][512] float and
+ * log-posteriors [cap][n_classes][512] float of the first min(cap, allocated) pool slots,
+ * in the slot order of map_download (zeros while the mode's pool does not exist); either
+ * may be NULL.  Returns the number of allocated blocks, -1 on error. */
+int64_t map_download_aux(map_t *map, int64_t cap, float *grad, float *logpost);
+/* Test access (synchronous): the last frame's normal image [rows * cols][4] float (world
+ * normal xyz and kept range w, zeros where the point filter dropped the return) under the
+ * non-projective distance; returns rows * cols, 0 in projective mode, -1 on error. */
+int64_t map_frame_normals(map_t *map, float *out, int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,8 @@ GEN = os.path.join(CSRC, "generated")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapcore.so")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["runtime.hip", "k_integrate.hip", "k_mesh.hip", "k_query.hip", "k_batch.hip", "k_range.hip"]
+SOURCES = ["runtime.hip", "k_integrate.hip", "k_mesh.hip", "k_query.hip", "k_batch.hip", "k_range.hip",
+           "k_quality.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

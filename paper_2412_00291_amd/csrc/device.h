@@ -270,19 +270,75 @@ __device__ __forceinline__ void lds_insert(unsigned long long *lk, const MapView
     frame_insert_direct(m, f, key);  // table full: straight to the frame set
 }
 
+// Normal image and point filter of the non-projective distance (Sec. IV-C.2; the filter
+// of Sec. V-C).  Pixel (k, c) back-projects to p = r d(k, c); its normal is the normalised
+// cross product (p1 - p) x (p2 - p) of the differences to the pixel above, (k - 1, c), and
+// the pixel to its left, (k, c - 1) with columns wrapping around the turn, turned to face
+// the sensor.  The top row and pixels whose own or neighbouring return is invalid have
+// none.  The return is kept when the angle between its ray and the normal is at most the
+// incidence limit (cosine >= cos_inc).  Returns the normal rotated into the world frame in
+// xyz and the kept range in w (all 0 when the return is not kept).  fp32, fixed order.
+__device__ __forceinline__ float4 pixel_normal(const LidarLUT &L, const Pose &T, const float *__restrict__ range,
+                                               int k, int c, float cos_inc)
+{
+    const int C = L.cols;
+    const int ku = k > 0 ? k - 1 : 0, cl = c == 0 ? C - 1 : c - 1;  // clamped: row 0 reads itself
+    const float r = range[k * C + c], r1 = range[ku * C + c], r2 = range[k * C + cl];
+    const float cek = L.ce[k], sek = L.se[k], ceu = L.ce[ku], seu = L.se[ku];
+    const float cpc = L.cp[c], spc = L.sp[c], cpl = L.cp[cl], spl = L.sp[cl];
+    float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (k == 0 || !valid_return(r, L.r_max) || !valid_return(r1, L.r_max) || !valid_return(r2, L.r_max)) return out;
+    const float dx = cek * cpc, dy = cek * spc, dz = sek;
+    const float px = r * dx, py = r * dy, pz = r * dz;
+    const float p1x = r1 * (ceu * cpc), p1y = r1 * (ceu * spc), p1z = r1 * seu;
+    const float p2x = r2 * (cek * cpl), p2y = r2 * (cek * spl), p2z = r2 * sek;
+    const float ax = p1x - px, ay = p1y - py, az = p1z - pz;
+    const float bx = p2x - px, by = p2y - py, bz = p2z - pz;
+    float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+    const float l2 = (nx * nx + ny * ny) + nz * nz;
+    if (!(l2 > 0.0f) || !isfinite(l2)) return out;
+    const float l = sqrt_rn(l2);
+    nx = nx / l;
+    ny = ny / l;
+    nz = nz / l;
+    float s = (nx * dx + ny * dy) + nz * dz;  // cosine between the normal and the ray
+    if (s > 0.0f) {
+        nx = -nx;
+        ny = -ny;
+        nz = -nz;
+        s = -s;
+    }
+    if (!(-s >= cos_inc)) return out;
+    out.x = (T.m[0] * nx + T.m[1] * ny) + T.m[2] * nz;
+    out.y = (T.m[4] * nx + T.m[5] * ny) + T.m[6] * nz;
+    out.z = (T.m[8] * nx + T.m[9] * ny) + T.m[10] * nz;
+    out.w = r;
+    return out;
+}
+
 // The band segment of one pixel's valid return, in 2^-16-voxel fixed point (voxel v
 // spans [v, v+1) after the half-voxel shift), walked block by block: at each step the
 // axis whose next block boundary comes first advances.  Moves in the positive direction
 // happen at the crossing parameter (the boundary plane belongs to the next block); moves
 // in the negative direction happen just after it.  Axes with equal parameter and
 // direction class move together, so a segment through an edge or corner skips the side
-// blocks exactly as the half-open cells require.
+// blocks exactly as the half-open cells require.  With the non-projective distance (kNP)
+// the pixel's normal and point filter come first (stored in the frame's normal image),
+// and the kept return is the one walked.
+template <bool kNP = false>
 __device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapView &m, const FrameView &f,
                                             const LidarLUT &L, const Pose &T, const float *__restrict__ range,
-                                            int pix)
+                                            int pix, float cos_inc = 0.0f)
 {
     const int k = pix / L.cols, c = pix - k * L.cols;
-    const float r = range[pix];
+    float r;
+    if (kNP) {
+        const float4 nr = pixel_normal(L, T, range, k, c, cos_inc);
+        f.nimg[pix] = nr;
+        r = nr.w;
+    } else {
+        r = range[pix];
+    }
     const float ce = L.ce[k], se = L.se[k], cp = L.cp[c], sp = L.sp[c];
     // the table reads wait here with the return (else the compiler moves them past the
     // validity test: a second round trip)
@@ -565,14 +621,16 @@ __device__ __forceinline__ int neighbour_slot(const MapView &m, int j, int3 bc, 
 // reads: project a voxel to its nearest pixel (-1 if none, with the sensor-frame
 // distance), then update from the pixel's return.
 
-// Nearest pixel (row * cols + col, or -1) of voxel li of the block at bc, and its distance.
+// Nearest pixel (row * cols + col, or -1) of voxel li of the block at bc, its distance,
+// and its offset from the sensor in the map frame (dv).
 __device__ __forceinline__ int tsdf_project(const MapView &m, const LidarLUT &L, const Pose &T, int3 bc, int li,
-                                            float &dist)
+                                            float &dist, float3 &dv)
 {
     const float nu = m.nu;
     const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
     const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
     const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
+    dv = make_float3(dx, dy, dz);
     const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
     const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
     const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
@@ -608,11 +666,55 @@ __device__ __forceinline__ bool tsdf_update(const MapView &m, const LidarLUT &L,
     return true;
 }
 
+// The non-projective update (Eq. 4 as read, Eq. 5): the weight is that of the projective
+// psi, the truncated value is the distance d = -psi u.(e + n) / (1 + n.e) clamped to
+// [-tau, tau], where u is the unit ray from the sensor to the voxel, n the normal of the
+// voxel's pixel (nr.xyz, kept range in nr.w) and e the voxel's gradient g, or n where
+// n.g <= 0 (no gradient yet, or one 90 degrees or more from the normal).  The gradient
+// becomes the normalised weighted average of the normals, (W g + w n) / |W g + w n|.
+// True if updated; band: |psi| <= tau.
+__device__ __forceinline__ bool tsdf_update_np(const MapView &m, const LidarLUT &L, float4 nr, float dist, float3 dv,
+                                               float2 &v, float3 &g, bool &band)
+{
+    const float tau = m.tau, two_tau = m.tau + m.tau;
+    band = false;
+    if (!valid_return(nr.w, L.r_max)) return false;
+    const float psi = nr.w - dist;
+    if (psi < -tau) return false;
+    const float a = psi + tau;
+    float w = 1.0f;
+    if (a < two_tau) w = a / two_tau;
+    if (w == 0.0f) return false;
+    const float ng = (nr.x * g.x + nr.y * g.y) + nr.z * g.z;
+    const bool use_g = ng > 0.0f;
+    const float ex = use_g ? g.x : nr.x, ey = use_g ? g.y : nr.y, ez = use_g ? g.z : nr.z;
+    const float ux = dv.x / dist, uy = dv.y / dist, uz = dv.z / dist;
+    const float hx = ex + nr.x, hy = ey + nr.y, hz = ez + nr.z;
+    const float uh = (ux * hx + uy * hy) + uz * hz;
+    const float ne = (nr.x * ex + nr.y * ey) + nr.z * ez;
+    const float d = -(psi * (uh / (1.0f + ne)));
+    const float gam = d >= 0.0f ? (d < tau ? d : tau) : (d > -tau ? d : -tau);
+    const float sx = v.y * g.x + w * nr.x, sy = v.y * g.y + w * nr.y, sz = v.y * g.z + w * nr.z;
+    const float l2 = (sx * sx + sy * sy) + sz * sz;
+    if (l2 > 0.0f && isfinite(l2)) {
+        const float l = sqrt_rn(l2);
+        g = make_float3(sx / l, sy / l, sz / l);
+    }
+    const float num = v.y * v.x + w * gam;
+    const float den = v.y + w;
+    v.x = num / den;
+    v.y = den;
+    band = fabsf(psi) <= tau;
+    return true;
+}
+
 // The TSDF update of one touched block's voxels by one worker of kWidth lanes (rank is
 // the lane's index in the worker); records the block's band bits.  Returns the updates.
 // The lane's (D, W) loads are issued first, then its projections (LDS tables), then all
-// of its range reads, so a block costs one memory round trip.
-template <int kWidth>
+// of its range reads, so a block costs one memory round trip.  With the non-projective
+// distance (kNP) the lane also loads its voxels' gradients with (D, W), and reads the
+// normal image (normal and kept range in one 16-byte load) in place of the range image.
+template <int kWidth, bool kNP = false>
 __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const FrameView &f, const LidarLUT &L,
                                                          const Pose &T, const float *__restrict__ range, int e,
                                                          unsigned long long key, int slot, int rank)
@@ -621,21 +723,39 @@ __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const
     constexpr int kV = kBlockVoxels / kWidth;
     const int3 bc = unpack_key(key);
     float2 *dwb = m.dw + (size_t)slot * kBlockVoxels;
+    float *gb = kNP ? m.grad + (size_t)slot * 3 * kBlockVoxels : nullptr;
     float2 v[kV];
+    float3 g[kV], dv[kV];
+    float4 nr[kV];
     int pix[kV];
     float dist[kV], r[kV];
 #pragma unroll
-    for (int it = 0; it < kV; ++it) v[it] = dwb[it * kWidth + rank];
+    for (int it = 0; it < kV; ++it) {
+        const int li = it * kWidth + rank;
+        v[it] = dwb[li];
+        if (kNP) g[it] = make_float3(gb[li], gb[kBlockVoxels + li], gb[2 * kBlockVoxels + li]);
+    }
 #pragma unroll
-    for (int it = 0; it < kV; ++it) pix[it] = tsdf_project(m, L, T, bc, it * kWidth + rank, dist[it]);
+    for (int it = 0; it < kV; ++it) pix[it] = tsdf_project(m, L, T, bc, it * kWidth + rank, dist[it], dv[it]);
 #pragma unroll
-    for (int it = 0; it < kV; ++it) r[it] = pix[it] >= 0 ? range[pix[it]] : 0.0f;
+    for (int it = 0; it < kV; ++it) {
+        if (kNP) nr[it] = pix[it] >= 0 ? f.nimg[pix[it]] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        else r[it] = pix[it] >= 0 ? range[pix[it]] : 0.0f;
+    }
     unsigned long long upd = 0;
 #pragma unroll
     for (int it = 0; it < kV; ++it) {
         const int li = it * kWidth + rank;
         bool band = false;
-        if (pix[it] >= 0 && tsdf_update(m, L, r[it], dist[it], v[it], band)) {
+        if (kNP) {
+            if (pix[it] >= 0 && tsdf_update_np(m, L, nr[it], dist[it], dv[it], v[it], g[it], band)) {
+                dwb[li] = v[it];
+                gb[li] = g[it].x;
+                gb[kBlockVoxels + li] = g[it].y;
+                gb[2 * kBlockVoxels + li] = g[it].z;
+                upd++;
+            }
+        } else if (pix[it] >= 0 && tsdf_update(m, L, r[it], dist[it], v[it], band)) {
             dwb[li] = v[it];
             upd++;
         }
@@ -849,10 +969,100 @@ __device__ __forceinline__ int label_voxel(const MapView &m, const CameraSet &cs
     return votes;
 }
 
+// Pixel (floor u, floor v) of the voxel centre x under a pinhole camera at pose T, as a
+// flat index into the image, or -1 when the voxel is behind the camera or off the image.
+__device__ __forceinline__ long long camera_pixel(const Camera &cam, const Pose &T, float x, float y, float z)
+{
+    const float dx = x - T.m[3], dy = y - T.m[7], dz = z - T.m[11];
+    const float px = (T.m[0] * dx + T.m[4] * dy) + T.m[8] * dz;
+    const float py = (T.m[1] * dx + T.m[5] * dy) + T.m[9] * dz;
+    const float pz = (T.m[2] * dx + T.m[6] * dy) + T.m[10] * dz;
+    if (!(pz > 0.0f)) return -1;
+    const float u = cam.fx * (px / pz) + cam.cx;
+    const float v = cam.fy * (py / pz) + cam.cy;
+    if (!(u >= 0.0f && u < (float)cam.width && v >= 0.0f && v < (float)cam.height)) return -1;
+    return (long long)(int)v * cam.width + (int)u;
+}
+
+// The latest label wins (the paper's Ours-wo-Bay ablation, Sec. V-C): a band voxel takes
+// the label of its latest observation, the last camera of the set that sees it with a
+// label below L; vote counts are untouched.  Returns the votes.
+__device__ __forceinline__ int label_voxel_latest(const MapView &m, const CameraSet &cs, int slot, int3 bc, int li)
+{
+    const size_t vi = (size_t)slot * kBlockVoxels + li;
+    const float nu = m.nu;
+    const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
+    const float x = (float)vx * nu, y = (float)vy * nu, z = (float)vz * nu;
+    int lab = -1, votes = 0;
+    for (int ci = 0; ci < cs.n; ++ci) {
+        const long long q = camera_pixel(cs.cam[ci], cs.T[ci], x, y, z);
+        if (q < 0) continue;
+        const int l = cs.img[ci][q];
+        if (l >= m.n_classes) continue;
+        lab = l;
+        votes++;
+    }
+    if (lab >= 0) m.fused[vi] = (uint8_t)lab;
+    return votes;
+}
+
+// Eq. 6 on a camera's per-pixel class log-probabilities o (logp [height][width][L]): a
+// band voxel seen at pixel q adds o(q) to its class log-posteriors and subtracts the
+// largest sum (the normaliser Z, which keeps the posterior's ratios and argmax and needs
+// no transcendental function); its most probable label is the class left at 0, the
+// lowest on ties.  Up to kLpRegs classes are held in registers between the two passes;
+// larger L recomputes the sums (the same fp32 values).  Returns 1 if the voxel voted.
+constexpr int kLpRegs = 32;
+__device__ __forceinline__ int logprob_voxel(const MapView &m, const Camera &cam, const Pose &T,
+                                             const float *__restrict__ logp, int slot, int3 bc, int li)
+{
+    const float nu = m.nu;
+    const int L = m.n_classes;
+    const int vx = 8 * bc.x + (li & 7), vy = 8 * bc.y + ((li >> 3) & 7), vz = 8 * bc.z + (li >> 6);
+    const long long q = camera_pixel(cam, T, (float)vx * nu, (float)vy * nu, (float)vz * nu);
+    if (q < 0) return 0;
+    const float *o = logp + (size_t)q * L;
+    float *lp = m.logpost + (size_t)slot * L * kBlockVoxels + li;
+    float mx = -INFINITY;
+    int best = -1;
+    if (L <= kLpRegs) {
+        float s[kLpRegs];
+#pragma unroll
+        for (int l = 0; l < kLpRegs; ++l) {
+            s[l] = 0.0f;
+            if (l < L) s[l] = lp[(size_t)l * kBlockVoxels] + o[l];
+        }
+#pragma unroll
+        for (int l = 0; l < kLpRegs; ++l)
+            if (l < L && s[l] > mx) mx = s[l];
+#pragma unroll
+        for (int l = 0; l < kLpRegs; ++l) {
+            if (l >= L) continue;
+            const float d = s[l] - mx;
+            lp[(size_t)l * kBlockVoxels] = d;
+            if (best < 0 && d == 0.0f) best = l;
+        }
+    } else {
+        for (int l = 0; l < L; ++l) {
+            const float sl = lp[(size_t)l * kBlockVoxels] + o[l];
+            if (sl > mx) mx = sl;
+        }
+        for (int l = 0; l < L; ++l) {
+            const float d = (lp[(size_t)l * kBlockVoxels] + o[l]) - mx;
+            lp[(size_t)l * kBlockVoxels] = d;
+            if (best < 0 && d == 0.0f) best = l;
+        }
+    }
+    m.fused[(size_t)slot * kBlockVoxels + li] = (uint8_t)best;
+    return 1;
+}
+
 // Label fusion from a label range image (the scan's points labelled by a point-cloud
 // segmentation): voxel li of the block at bc (slot `slot`) takes the label at its nearest
 // pixel of the scan model under pose T (the pixel rule of the projective update) and votes
-// with the rule of the camera labels.  Returns 1 if it voted.
+// with the rule of the camera labels (kLatest: the latest label wins).  Returns 1 if it
+// voted.
+template <bool kLatest = false>
 __device__ __forceinline__ int label_voxel_lidar(const MapView &m, const LidarLUT &L, const Pose &T,
                                                  const uint8_t *__restrict__ img, int slot, int3 bc, int li)
 {
@@ -868,6 +1078,10 @@ __device__ __forceinline__ int label_voxel_lidar(const MapView &m, const LidarLU
     const int l = img[(size_t)row * L.cols + col];
     if (l >= m.n_classes) return 0;
     const size_t vi = (size_t)slot * kBlockVoxels + li;
+    if (kLatest) {
+        m.fused[vi] = (uint8_t)l;
+        return 1;
+    }
     uint16_t *cnt = m.counts + (size_t)slot * m.n_classes * kBlockVoxels + li;
     unsigned c = cnt[(size_t)l * kBlockVoxels];
     if (c < 65535u) c++;

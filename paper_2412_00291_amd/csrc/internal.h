@@ -86,6 +86,10 @@ struct MapView {
     int32_t *mesh_nbr;        // [max_blocks][8] slots of b + e, e in {0,1}^3 (-1: absent), same
     unsigned long long *vmask;  // [max_blocks][16] per z slice: sign bits (D < 0), then observed
                                 // bits (W > 0), bit y * 8 + x; kept by the TSDF pass
+    float *grad;              // [max_blocks][3][512] unit distance gradient of the non-projective
+                              // distance (x, y, z planes); null until that distance is enabled
+    float *logpost;           // [max_blocks][L][512] class log-posteriors of Bayesian label fusion
+                              // (largest 0); null until that fusion is enabled
     Counters *ctr;
     SyncState *sync;
     uint32_t hmask;
@@ -120,6 +124,9 @@ struct FrameView {
     int32_t *tk_rank;           // [tk_cap] rank among new blocks
     int32_t *tk_fslot;          // [tk_cap] frame-set slot (cleared at frame end)
     unsigned long long *band;   // [tk_cap][8] band bits (|psi| <= tau) per voxel
+    float4 *nimg;               // [rows * cols] non-projective distance: the scan's world-frame
+                                // normals (xyz) and kept ranges (w, 0 where the point filter
+                                // drops the return); null in projective mode
     uint32_t fmask;
     int32_t tk_cap;
 };
@@ -244,12 +251,21 @@ hipError_t launch_batch(BatchMap *maps, BatchCtl *ctl, BatchSync *sync, MeshScan
 
 hipError_t launch_init_pool(const MapView &m, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t s);
+// Distance of the TSDF update: the projective psi (the paper's Ours-Proj), or the
+// non-projective distance of Eq. 4 with its normal image and point filter (Ours).
+constexpr int kDistProjective = 0, kDistNonProjective = 1;
+// Label fusion: vote counts (Eq. 6 with hard labels), the latest label (Ours-wo-Bay), or
+// Eq. 6 on per-pixel class log-probabilities.
+constexpr int kLabelCounts = 0, kLabelLatest = 1, kLabelBayes = 2;
+
 hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                        const float *range, hipStream_t s);
+                        const float *range, int dist_mode, float cos_inc, hipStream_t s);
 hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                       const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s);
+                       const float *range, uint32_t frame_id, int schedule, int grid, int dist_mode, hipStream_t s);
 hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int schedule, int grid,
-                         hipStream_t s);
+                         int label_mode, hipStream_t s);
+hipError_t launch_logprobs(const MapView &m, const FrameView &f, const Camera &cam, const Pose &T, const float *logp,
+                           int grid, hipStream_t s);
 // Workgroups of the meshing passes: the emitting pass's grid and the counting pass's,
 // a multiple of it (each the device-resident grid of its kernel).
 struct MeshGrid {
@@ -264,9 +280,29 @@ hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, i
 hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan,
                               MeshReport *report, int schedule, MeshGrid grid, hipStream_t s);
 hipError_t launch_labels_lidar(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                               const uint8_t *img, int grid, hipStream_t s);
+                               const uint8_t *img, int grid, int label_mode, hipStream_t s);
 hipError_t launch_range_image(const LidarLUT &lut, const float *pts, int n, float F, float O,
                               unsigned long long *keys, float *depth, float *height, hipStream_t s);
+// Uniform grid of a point cloud for capped nearest-neighbour queries (map-quality metrics):
+// occupied cells in an open-addressing hash with their point counts and the offsets of
+// their runs in pts (the cloud's points in cell order, point index bits in w).
+struct CellGrid {
+    unsigned long long *key;  // [mask + 1] packed cell coordinates (all ones: free)
+    uint32_t *count;          // [mask + 1] points per cell (zeroed before the build)
+    uint32_t *offset;         // [mask + 1] first point of the cell's run
+    uint32_t *cursor;         // [mask + 1] fill cursor (zeroed before the build)
+    uint32_t *slot_of;        // [n] cell slot of each point
+    float4 *pts;              // [n] points in cell order
+    uint32_t mask;
+    double inv_h;             // 1 / cell edge
+};
+hipError_t launch_grid_build(CellGrid &g, const float *p, long long n, uint32_t *scan_tmp, hipStream_t s);
+hipError_t launch_grid_query(const CellGrid &g, const float *q, long long n, double cap, double *dist, long long *nn,
+                             hipStream_t s);
+hipError_t launch_quality(const double *dM, long long nM, const double *dG, const long long *nnG, long long nG,
+                          const uint8_t *labM, const uint8_t *labG, int L, double cap, double *partial, int nparts,
+                          unsigned long long *conf, double *out, hipStream_t s);
+
 hipError_t launch_query(const MapView &m, const float *pts, long long n, float *sdf, float *grad,
                         uint8_t *valid, hipStream_t s);
 hipError_t launch_adjoint(const MapView &m, const float *xi, const float *pts, int B, long long N,

@@ -46,8 +46,11 @@ hipError_t launch_init_pool(const MapView &m, hipStream_t s)
 // allocation: one thread per pixel, the workgroup's blocks de-duplicated in LDS
 // ---------------------------------------------------------------------------------
 
+// kNP: the non-projective distance, whose normal image and point filter are computed here
+// (one pixel per thread, stored in the frame's normal image for the TSDF pass).
+template <bool kNP>
 __global__ __launch_bounds__(kThreads) void k_alloc(MapView m, FrameView f, LidarLUT L, Pose T,
-                                                   const float *__restrict__ range)
+                                                   const float *__restrict__ range, float cos_inc)
 {
     __shared__ unsigned long long lk[kLdsKeys];
     __shared__ int s_tmp[kThreads / 64];
@@ -55,17 +58,20 @@ __global__ __launch_bounds__(kThreads) void k_alloc(MapView m, FrameView f, Lida
     for (int i = threadIdx.x; i < kLdsKeys; i += kThreads) lk[i] = kEmpty;
     __syncthreads();
     const int pix = blockIdx.x * kThreads + threadIdx.x;
-    if (pix < L.rows * L.cols) alloc_pixel(lk, m, f, L, T, range, pix);
+    if (pix < L.rows * L.cols) alloc_pixel<kNP>(lk, m, f, L, T, range, pix, cos_inc);
     __syncthreads();
     alloc_flush(lk, s_tmp, &s_base, m, f);
 }
 
 hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                        const float *range, hipStream_t s)
+                        const float *range, int dist_mode, float cos_inc, hipStream_t s)
 {
     int npix = lut.rows * lut.cols;
     int grid = (npix + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_alloc, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range);
+    if (dist_mode == kDistNonProjective)
+        hipLaunchKernelGGL(k_alloc<true>, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, cos_inc);
+    else
+        hipLaunchKernelGGL(k_alloc<false>, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, cos_inc);
     return hipGetLastError();
 }
 
@@ -81,7 +87,7 @@ hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lu
 // workgroup copies them (cols + rows + 1 pairs, 17 KiB for 2048 columns) into dynamic LDS
 // when the launch provides it (kLdsLut), so that the range image is the voxel's only
 // global read on the way to its update.
-template <int kSched, bool kLdsLut>
+template <int kSched, bool kLdsLut, bool kNP>
 __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, LidarLUT L, Pose T,
                                                   const float *__restrict__ range, uint32_t frame_id)
 {
@@ -111,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
                 const int e = base + j * stride;
                 if (e >= fs.n_list) break;
                 const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
-                my_updates += tsdf_block<kWidth>(m, f, L, T, range, e, f.tk_key[e], slot, rank);
+                my_updates += tsdf_block<kWidth, kNP>(m, f, L, T, range, e, f.tk_key[e], slot, rank);
             }
             // dirty marks last: nothing above waits for their hash probes
             const int i = rank >> 3;  // lane r marks neighbour r % 8 of entry r / 8
@@ -137,21 +143,29 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
     if (s_last && wave == 0) close_frame_wave(m, fs);
 }
 
-hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                       const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s)
+template <bool kNP>
+static void launch_tsdf_t(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                          const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s)
 {
     const size_t lds = ((size_t)lut.cols + lut.rows + 1) * sizeof(float2);
     if (lds <= kMaxLdsLut) {
         if (schedule == 0)
-            hipLaunchKernelGGL((k_tsdf<0, true>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<0, true, kNP>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
         else
-            hipLaunchKernelGGL((k_tsdf<1, true>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<1, true, kNP>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
     } else {
         if (schedule == 0)
-            hipLaunchKernelGGL((k_tsdf<0, false>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<0, false, kNP>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
         else
-            hipLaunchKernelGGL((k_tsdf<1, false>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<1, false, kNP>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
     }
+}
+
+hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                       const float *range, uint32_t frame_id, int schedule, int grid, int dist_mode, hipStream_t s)
+{
+    if (dist_mode == kDistNonProjective) launch_tsdf_t<true>(m, f, lut, T, range, frame_id, schedule, grid, s);
+    else launch_tsdf_t<false>(m, f, lut, T, range, frame_id, schedule, grid, s);
     return hipGetLastError();
 }
 
@@ -161,8 +175,12 @@ hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut
 // band voxels compacted (about one in ten voxels is in the band); schedules as above
 // ---------------------------------------------------------------------------------
 
-template <int kSched>
-__global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, CameraSet cs)
+// The band voxels of the last frame's touched entries, each passed to vote(slot, bc, li)
+// (which returns its votes); the votes go to the map's spread counter.  kSched 0: a
+// workgroup takes its entries blockIdx + j G kLabGroup at a time with their voxels as one
+// flat list; kSched 1: a wavefront takes one entry at a time.
+template <int kSched, class Vote>
+__device__ __forceinline__ void for_band_voxels(const MapView &m, const FrameView &f, Vote vote)
 {
     __shared__ unsigned long long s_sum[kThreads / 64];
     __shared__ LabelGroup g;
@@ -170,7 +188,6 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long my_votes = 0;
     if (kSched == 0) {
-        // workgroup: its entries blockIdx + j G, kLabGroup at a time, voxels as one flat list
         const int G = (int)gridDim.x;
         for (int e0 = blockIdx.x; e0 < n; e0 += kLabGroup * G) {
             {  // all of the group's reads at once (clamped indices, masked after)
@@ -205,47 +222,19 @@ __global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, Cam
             for (int t = threadIdx.x; t < epre[kLabGroup]; t += kThreads) {
                 int j, li;
                 label_group_voxel(g, epre, t, j, li);
-                my_votes += label_voxel(m, cs, g.slot[j], unpack_key(g.key[j]), li);
+                my_votes += vote(g.slot[j], unpack_key(g.key[j]), li);
             }
             __syncthreads();  // the group's LDS is rewritten by the next group
         }
     } else {
-        // wavefront: one entry at a time
         const int first = (int)blockIdx.x * (kThreads / 64) + wave, stride = (int)gridDim.x * (kThreads / 64);
         for (int e = first; e < n; e += stride) {
             const int slot = f.tk_slot[e];
             const int3 bc = unpack_key(f.tk_key[e]);
             const BandWords b = band_words(f, e);
 #pragma unroll 1
-            for (int t = lane; t < b.pre[8]; t += 64) my_votes += label_voxel(m, cs, slot, bc, band_select(b, t));
+            for (int t = lane; t < b.pre[8]; t += 64) my_votes += vote(slot, bc, band_select(b, t));
         }
-    }
-    unsigned long long w = wave_sum_u64(my_votes);
-    if (lane == 0) s_sum[wave] = w;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int i = 0; i < kThreads / 64; ++i) t += s_sum[i];
-        if (t) spread_add(m.sync->votes, t);
-    }
-}
-
-// label fusion from a label range image under the scan model: a wavefront per touched
-// block, its band voxels compacted
-__global__ __launch_bounds__(kThreads) void k_labels_lidar(MapView m, FrameView f, LidarLUT L, Pose T,
-                                                           const uint8_t *__restrict__ img)
-{
-    __shared__ unsigned long long s_sum[kThreads / 64];
-    const int n = m.ctr->last_touched;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long my_votes = 0;
-    const int first = (int)blockIdx.x * (kThreads / 64) + wave, stride = (int)gridDim.x * (kThreads / 64);
-    for (int e = first; e < n; e += stride) {
-        const int slot = f.tk_slot[e];
-        const int3 bc = unpack_key(f.tk_key[e]);
-        const BandWords b = band_words(f, e);
-#pragma unroll 1
-        for (int t = lane; t < b.pre[8]; t += 64) my_votes += label_voxel_lidar(m, L, T, img, slot, bc, band_select(b, t));
     }
     const unsigned long long w = wave_sum_u64(my_votes);
     if (lane == 0) s_sum[wave] = w;
@@ -257,18 +246,62 @@ __global__ __launch_bounds__(kThreads) void k_labels_lidar(MapView m, FrameView 
     }
 }
 
-hipError_t launch_labels_lidar(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                               const uint8_t *img, int grid, hipStream_t s)
+// Camera labels for every camera of the call, in order (equal to one call per camera: a
+// voxel's votes are sequential): vote counts (kLatest false) or the latest label.
+template <int kSched, bool kLatest>
+__global__ __launch_bounds__(kThreads) void k_labels(MapView m, FrameView f, CameraSet cs)
 {
-    hipLaunchKernelGGL(k_labels_lidar, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, img);
+    for_band_voxels<kSched>(m, f, [&](int slot, int3 bc, int li) {
+        return kLatest ? label_voxel_latest(m, cs, slot, bc, li) : label_voxel(m, cs, slot, bc, li);
+    });
+}
+
+// label fusion from a label range image under the scan model: a wavefront per touched
+// block, its band voxels compacted
+template <bool kLatest>
+__global__ __launch_bounds__(kThreads) void k_labels_lidar(MapView m, FrameView f, LidarLUT L, Pose T,
+                                                           const uint8_t *__restrict__ img)
+{
+    for_band_voxels<1>(m, f, [&](int slot, int3 bc, int li) {
+        return label_voxel_lidar<kLatest>(m, L, T, img, slot, bc, li);
+    });
+}
+
+// Eq. 6 on one camera's class log-probability image, over the band voxels of the last frame
+__global__ __launch_bounds__(kThreads) void k_logprobs(MapView m, FrameView f, Camera cam, Pose T,
+                                                       const float *__restrict__ logp)
+{
+    for_band_voxels<0>(m, f, [&](int slot, int3 bc, int li) { return logprob_voxel(m, cam, T, logp, slot, bc, li); });
+}
+
+hipError_t launch_labels_lidar(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                               const uint8_t *img, int grid, int label_mode, hipStream_t s)
+{
+    if (label_mode == kLabelLatest)
+        hipLaunchKernelGGL(k_labels_lidar<true>, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, img);
+    else
+        hipLaunchKernelGGL(k_labels_lidar<false>, dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, img);
     return hipGetLastError();
 }
 
 hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int schedule, int grid,
-                         hipStream_t s)
+                         int label_mode, hipStream_t s)
 {
-    if (schedule == 0) hipLaunchKernelGGL(k_labels<0>, dim3(grid), dim3(kThreads), 0, s, m, f, cams);
-    else hipLaunchKernelGGL(k_labels<1>, dim3(grid), dim3(kThreads), 0, s, m, f, cams);
+    const bool latest = label_mode == kLabelLatest;
+    if (schedule == 0) {
+        if (latest) hipLaunchKernelGGL((k_labels<0, true>), dim3(grid), dim3(kThreads), 0, s, m, f, cams);
+        else hipLaunchKernelGGL((k_labels<0, false>), dim3(grid), dim3(kThreads), 0, s, m, f, cams);
+    } else {
+        if (latest) hipLaunchKernelGGL((k_labels<1, true>), dim3(grid), dim3(kThreads), 0, s, m, f, cams);
+        else hipLaunchKernelGGL((k_labels<1, false>), dim3(grid), dim3(kThreads), 0, s, m, f, cams);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_logprobs(const MapView &m, const FrameView &f, const Camera &cam, const Pose &T, const float *logp,
+                           int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_logprobs, dim3(grid), dim3(kThreads), 0, s, m, f, cam, T, logp);
     return hipGetLastError();
 }
 

@@ -47,6 +47,11 @@ struct map_s {
     unsigned long long *rkeys = nullptr;
     int64_t rkeys_n = 0;
     bool rkeys_dirty = false;  // a failed call may have left keys set
+    // distance and label-fusion modes (kDist*, kLabel*) and their buffers
+    int dist_mode = kDistProjective;
+    float cos_inc = 0.0f;      // point filter of the non-projective distance
+    int64_t nimg_n = 0;        // pixels of the normal image (FrameView::nimg)
+    int label_mode = kLabelCounts;
     // adjoint partial sums
     float *partial = nullptr;
     size_t partial_floats = 0;
@@ -115,8 +120,8 @@ static void free_all(map_t *m)
     m->prof_free.clear();
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hash,
                     m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
-                    m->f.tk_fslot, m->f.band, m->lut_buf, m->partial, m->scan.wg_tris, m->scan.wg_blocks,
-                    m->scan.wg_off, m->rkeys};
+                    m->f.tk_fslot, m->f.band, m->f.nimg, m->v.grad, m->v.logpost, m->lut_buf, m->partial,
+                    m->scan.wg_tris, m->scan.wg_blocks, m->scan.wg_off, m->rkeys};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (m->h_ctr) (void)hipHostFree(m->h_ctr);
@@ -385,13 +390,23 @@ static int ensure_frame_scratch(map_t *m, const lidar_model *L, hipStream_t s)
     const int64_t per_ray = 1 + 3 * ((int64_t)std::floor(band_vox / 8.0) + 2);
     const int64_t need = (int64_t)L->rows * L->cols * per_ray;
     if (need > (int64_t)1 << 30) return fail(m, MAP_ERR_INVALID_ARG, "lidar: image too large");
+    if (m->dist_mode == kDistNonProjective && (int64_t)L->rows * L->cols > m->nimg_n) {
+        HIP_TRY(m, hipStreamSynchronize(s));
+        if (m->f.nimg) HIP_TRY(m, hipFree(m->f.nimg));
+        m->f.nimg = nullptr;
+        m->nimg_n = 0;
+        HIP_TRY(m, hipMalloc(&m->f.nimg, (size_t)L->rows * L->cols * sizeof(float4)));
+        m->nimg_n = (int64_t)L->rows * L->cols;
+    }
     if (m->f.tk_cap >= need) return MAP_OK;
     HIP_TRY(m, hipStreamSynchronize(s));
     FrameView &f = m->f;
     void *old[] = {f.fkeys, f.tk_key, f.tk_slot, f.tk_rank, f.tk_fslot, f.band};
     for (void *p : old)
         if (p) HIP_TRY(m, hipFree(p));
+    float4 *nimg = f.nimg;  // kept (sized separately)
     f = FrameView{};
+    f.nimg = nimg;
     const uint64_t fcap = next_pow2((uint64_t)(2 * need));
     HIP_TRY(m, hipMalloc(&f.fkeys, fcap * sizeof(unsigned long long)));
     HIP_TRY(m, hipMalloc(&f.tk_key, need * sizeof(unsigned long long)));
@@ -432,10 +447,13 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     rc = ensure_frame_scratch(m, L, s);
     if (rc) return rc;
     const Pose T = to_pose(T_wl);
-    HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] { return launch_alloc(m->v, m->f, m->lut, T, range_dev, s); }));
+    HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] {
+        return launch_alloc(m->v, m->f, m->lut, T, range_dev, m->dist_mode, m->cos_inc, s);
+    }));
     const uint32_t fid = m->frame_id++;
     HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
-        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, m->tsdf_grid), s);
+        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, m->tsdf_grid),
+                           m->dist_mode, s);
     }));
     m->last_stream = s;
     m->has_scan = true;
@@ -458,6 +476,8 @@ extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_mode
         if (!camera_ok(&cams[i])) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: bad camera model %d", i);
         if (!pose_ok(T_wc + 16 * i)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: pose %d is not rigid", i);
     }
+    if (m->label_mode == kLabelBayes)
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels: the map fuses log-probability images");
     if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels: no LiDAR frame integrated yet");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
@@ -471,7 +491,7 @@ extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_mode
             cs.img[j] = labels_dev[i0 + j];
         }
         HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
-            return launch_labels(m->v, m->f, cs, m->sched[1], grid_for(m->f.tk_cap, 1, 2048), s);
+            return launch_labels(m->v, m->f, cs, m->sched[1], grid_for(m->f.tk_cap, 1, 2048), m->label_mode, s);
         }));
     }
     m->last_stream = s;
@@ -488,6 +508,8 @@ extern "C" int map_integrate_labels_lidar(map_t *m, const lidar_model *L, const 
     if (!(L->r_max > 0.0f) || !std::isfinite(L->r_max))
         return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: r_max must be positive and finite");
     if (!pose_ok(T_wl)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: pose is not a rigid transform");
+    if (m->label_mode == kLabelBayes)
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: the map fuses log-probability images");
     if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels_lidar: no LiDAR frame integrated yet");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
@@ -495,7 +517,63 @@ extern "C" int map_integrate_labels_lidar(map_t *m, const lidar_model *L, const 
     if (rc) return rc;
     const Pose T = to_pose(T_wl);
     HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
-        return launch_labels_lidar(m->v, m->f, m->lut, T, labels_dev, grid_for(m->f.tk_cap, 1, 2048), s);
+        return launch_labels_lidar(m->v, m->f, m->lut, T, labels_dev, grid_for(m->f.tk_cap, 1, 2048), m->label_mode,
+                                   s);
+    }));
+    m->last_stream = s;
+    return MAP_OK;
+}
+
+extern "C" int map_set_distance(map_t *m, int32_t mode, float max_incidence)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if ((mode != MAP_DIST_PROJECTIVE && mode != MAP_DIST_NONPROJECTIVE) || !std::isfinite(max_incidence) ||
+        max_incidence < 0.0f)
+        return fail(m, MAP_ERR_INVALID_ARG, "set_distance: mode 0 or 1 and a finite max_incidence >= 0");
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    if (mode == MAP_DIST_NONPROJECTIVE && !m->v.grad) {
+        const size_t bytes = (size_t)m->p.max_blocks * 3 * kBlockVoxels * sizeof(float);
+        HIP_TRY(m, hipStreamSynchronize(m->last_stream));
+        HIP_TRY(m, hipMalloc(&m->v.grad, bytes));
+        HIP_TRY(m, hipMemset(m->v.grad, 0, bytes));
+    }
+    m->dist_mode = mode;
+    m->cos_inc = (float)std::cos((double)max_incidence);
+    return MAP_OK;
+}
+
+extern "C" int map_set_label_fusion(map_t *m, int32_t mode)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (mode != MAP_LABELS_COUNTS && mode != MAP_LABELS_LATEST && mode != MAP_LABELS_BAYES)
+        return fail(m, MAP_ERR_INVALID_ARG, "set_label_fusion: mode 0, 1 or 2");
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    if (mode == MAP_LABELS_BAYES && !m->v.logpost) {
+        const size_t bytes = (size_t)m->p.max_blocks * m->p.n_classes * kBlockVoxels * sizeof(float);
+        HIP_TRY(m, hipStreamSynchronize(m->last_stream));
+        HIP_TRY(m, hipMalloc(&m->v.logpost, bytes));
+        HIP_TRY(m, hipMemset(m->v.logpost, 0, bytes));
+    }
+    m->label_mode = mode;
+    return MAP_OK;
+}
+
+extern "C" int map_integrate_logprobs(map_t *m, const camera_model *cam, const float *logp_dev, const float T_wc[16],
+                                      void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (!cam || !logp_dev || !T_wc) return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: NULL argument");
+    if (!camera_ok(cam)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: bad camera model");
+    if (!pose_ok(T_wc)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: pose is not a rigid transform");
+    if (m->label_mode != kLabelBayes)
+        return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: the map's label fusion is not Bayesian (mode 2)");
+    if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_logprobs: no LiDAR frame integrated yet");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    const Camera c{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+    const Pose T = to_pose(T_wc);
+    HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
+        return launch_logprobs(m->v, m->f, c, T, logp_dev, grid_for(m->f.tk_cap, 1, 2048), s);
     }));
     m->last_stream = s;
     return MAP_OK;
@@ -625,6 +703,107 @@ extern "C" int map_sdf_pose_adjoint(map_t *m, const float *xi_dev, const float *
     return MAP_OK;
 }
 
+// ---------------------------------------------------------------------------------
+// map-quality metrics (Sec. V-C, Eq. 7, Eq. 8)
+// ---------------------------------------------------------------------------------
+
+namespace {
+struct DevBuffers {  // device scratch of one call, freed on every return path
+    std::vector<void *> ptrs;
+    ~DevBuffers()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t get(T **out, size_t count)
+    {
+        *out = nullptr;
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) {
+            ptrs.push_back(p);
+            *out = static_cast<T *>(p);
+        }
+        return e;
+    }
+};
+}  // namespace
+
+extern "C" int map_mesh_quality(const float *mesh_pts_dev, const uint8_t *mesh_lab_dev, int64_t n_mesh,
+                                const float *gt_pts_dev, const uint8_t *gt_lab_dev, int64_t n_gt, float voxel_size,
+                                int32_t n_classes, int32_t device, double *d_mesh_dev, double *d_gt_dev,
+                                int64_t *nn_gt_dev, int64_t *confusion_host, map_quality *out, void *stream)
+{
+    if (!out || n_mesh < 0 || n_gt < 0 || n_mesh > INT32_MAX || n_gt > INT32_MAX ||
+        (n_mesh > 0 && (!mesh_pts_dev || !mesh_lab_dev)) || (n_gt > 0 && (!gt_pts_dev || !gt_lab_dev)))
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "mesh_quality: bad arguments");
+    if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size) || n_classes < 1 || n_classes > 254)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "mesh_quality: need voxel_size > 0 and n_classes in [1, 254]");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, MAP_ERR_INVALID_ARG, "mesh_quality: device %d not available", device);
+#define Q_TRY(expr)                                                                                         \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail(nullptr, MAP_ERR_DEVICE, "mesh_quality: %s: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+    Q_TRY(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    const double cap = 2.0 * (double)voxel_size;
+    DevBuffers buf;
+    // a grid per cloud: cells a little larger than the cap, so every point within the cap
+    // of a query lies in one of the 27 cells around it whatever the rounding of x / h
+    auto make_grid = [&](CellGrid &g, const float *p, int64_t n) -> hipError_t {
+        const uint64_t slots = next_pow2(std::max<uint64_t>(2 * (uint64_t)n, 1024));
+        g.mask = (uint32_t)(slots - 1);
+        g.inv_h = 1.0 / (cap * (1.0 + 1e-6));
+        hipError_t e;
+        if ((e = buf.get(&g.key, slots)) != hipSuccess || (e = buf.get(&g.count, slots)) != hipSuccess ||
+            (e = buf.get(&g.offset, slots)) != hipSuccess || (e = buf.get(&g.cursor, slots)) != hipSuccess ||
+            (e = buf.get(&g.slot_of, (size_t)n)) != hipSuccess || (e = buf.get(&g.pts, (size_t)n)) != hipSuccess)
+            return e;
+        uint32_t *scan_tmp = nullptr;
+        if ((e = buf.get(&scan_tmp, (slots + 255) / 256)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(g.key, 0xFF, slots * sizeof(unsigned long long), s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(g.count, 0, slots * sizeof(uint32_t), s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(g.cursor, 0, slots * sizeof(uint32_t), s)) != hipSuccess) return e;
+        return launch_grid_build(g, p, n, scan_tmp, s);
+    };
+    double *dM = d_mesh_dev, *dG = d_gt_dev;
+    long long *nnG = reinterpret_cast<long long *>(nn_gt_dev);
+    if (!dM) Q_TRY(buf.get(&dM, (size_t)n_mesh));
+    if (!dG) Q_TRY(buf.get(&dG, (size_t)n_gt));
+    if (!nnG) Q_TRY(buf.get(&nnG, (size_t)n_gt));
+    CellGrid gG{}, gM{};
+    Q_TRY(make_grid(gG, gt_pts_dev, n_gt));
+    Q_TRY(launch_grid_query(gG, mesh_pts_dev, n_mesh, cap, dM, nullptr, s));
+    Q_TRY(make_grid(gM, mesh_pts_dev, n_mesh));
+    Q_TRY(launch_grid_query(gM, gt_pts_dev, n_gt, cap, dG, nnG, s));
+    const int L = n_classes;
+    const int nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (std::max(n_mesh, n_gt) + 255) / 256));
+    double *partial = nullptr, *res = nullptr;
+    unsigned long long *conf = nullptr;
+    Q_TRY(buf.get(&partial, (size_t)nparts * 4));
+    Q_TRY(buf.get(&res, 6));
+    Q_TRY(buf.get(&conf, (size_t)(L + 1) * L));
+    Q_TRY(hipMemsetAsync(conf, 0, (size_t)(L + 1) * L * sizeof(unsigned long long), s));
+    Q_TRY(launch_quality(dM, n_mesh, dG, nnG, n_gt, mesh_lab_dev, gt_lab_dev, L, cap, partial, nparts, conf, res, s));
+    double h_res[6];
+    Q_TRY(hipMemcpyAsync(h_res, res, sizeof(h_res), hipMemcpyDeviceToHost, s));
+    if (confusion_host)
+        Q_TRY(hipMemcpyAsync(confusion_host, conf, (size_t)(L + 1) * L * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    Q_TRY(hipStreamSynchronize(s));
+#undef Q_TRY
+    out->re = h_res[0];
+    out->cd = h_res[1];
+    out->rc = h_res[2];
+    out->miou = h_res[3];
+    out->acc = h_res[4];
+    out->n_eval = (int64_t)h_res[5];
+    return MAP_OK;
+}
+
 static int read_counters(map_t *m)
 {
     HIP_TRY(m, hipSetDevice(m->p.device));
@@ -730,6 +909,42 @@ extern "C" int64_t map_download(map_t *m, int64_t cap, int32_t *coords, float *D
     if (fused && hipMemcpy(fused, m->v.fused, (size_t)k * kBlockVoxels, hipMemcpyDeviceToHost) != hipSuccess) return -1;
     if (counts && hipMemcpy(counts, m->v.counts, (size_t)k * m->p.n_classes * kBlockVoxels * sizeof(uint16_t),
                             hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+    return n;
+}
+
+extern "C" int64_t map_download_aux(map_t *m, int64_t cap, float *grad, float *logpost)
+{
+    if (!m || read_counters(m)) return -1;
+    const int64_t n = m->h_ctr->pool_used;
+    const int64_t k = std::min(n, cap);
+    if (k <= 0) return n;
+    const size_t gb = (size_t)k * 3 * kBlockVoxels * sizeof(float);
+    const size_t lb = (size_t)k * m->p.n_classes * kBlockVoxels * sizeof(float);
+    if (grad) {
+        if (m->v.grad) {
+            if (hipMemcpy(grad, m->v.grad, gb, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+        } else {
+            std::memset(grad, 0, gb);
+        }
+    }
+    if (logpost) {
+        if (m->v.logpost) {
+            if (hipMemcpy(logpost, m->v.logpost, lb, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+        } else {
+            std::memset(logpost, 0, lb);
+        }
+    }
+    return n;
+}
+
+extern "C" int64_t map_frame_normals(map_t *m, float *out, int64_t cap)
+{
+    if (!m || read_counters(m)) return -1;
+    if (m->dist_mode != kDistNonProjective || !m->f.nimg) return 0;
+    const int64_t n = (int64_t)m->lut_rows * m->lut_cols;
+    const int64_t k = std::min(n, cap);
+    if (k > 0 && out && hipMemcpy(out, m->f.nimg, (size_t)k * sizeof(float4), hipMemcpyDeviceToHost) != hipSuccess)
         return -1;
     return n;
 }
@@ -887,6 +1102,10 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
         for (int c = 0; c < it.n_cams; ++c)
             if (!it.labels_dev[c] || !camera_ok(&it.cams[c]) || !pose_ok(it.T_wc + 16 * c))
                 return fail(m, MAP_ERR_INVALID_ARG, "map_batch_step: bad camera %d of item %d", c, i);
+        if (m->dist_mode != kDistProjective || m->label_mode != kLabelCounts)
+            return fail(m, MAP_ERR_INVALID_ARG,
+                        "map_batch_step: map %d is not in the plain modes (projective distance, vote counts)",
+                        it.map_index);
     }
     int tiles = 0;
     for (int i = 0; i < n; ++i) {

@@ -18,6 +18,8 @@ _LIB_FILE = os.path.join(_HERE, "libmapcore.so")
 MAP_OK, MAP_ERR_INVALID_ARG, MAP_ERR_CAPACITY = 0, -1, -2
 MAP_ERR_BUFFER_TOO_SMALL, MAP_ERR_NO_SCAN, MAP_ERR_DEVICE = -3, -4, -5
 MAP_MESH_DIRTY, MAP_MESH_ALL = 0, 1
+MAP_DIST_PROJECTIVE, MAP_DIST_NONPROJECTIVE = 0, 1
+MAP_LABELS_COUNTS, MAP_LABELS_LATEST, MAP_LABELS_BAYES = 0, 1, 2
 
 
 def lib_path() -> str:
@@ -58,6 +60,11 @@ class _BatchItem(ctypes.Structure):
                 ("lab_dev", ctypes.c_void_p), ("edge_keys_dev", ctypes.c_void_p), ("cap_tris", ctypes.c_int64)]
 
 
+class _Quality(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("cd", ctypes.c_double), ("rc", ctypes.c_double),
+                ("miou", ctypes.c_double), ("acc", ctypes.c_double), ("n_eval", ctypes.c_int64)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("touched", "new_blocks", "updates", "votes", "mesh_blocks",
                                               "triangles", "allocated", "frames")]
@@ -90,6 +97,13 @@ _sig = {
     "map_batch_step": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
     "map_batch_destroy": (None, [_P]),
     "map_profile_read": (ctypes.c_int, [_P, _P, _P]),
+    "map_set_distance": (ctypes.c_int, [_P, _I32, ctypes.c_float]),
+    "map_set_label_fusion": (ctypes.c_int, [_P, _I32]),
+    "map_integrate_logprobs": (ctypes.c_int, [_P, ctypes.POINTER(_Camera), _P, _P, _P]),
+    "map_download_aux": (_I64, [_P, _I64, _P, _P]),
+    "map_frame_normals": (_I64, [_P, _P, _I64]),
+    "map_mesh_quality": (ctypes.c_int, [_P, _P, _I64, _P, _P, _I64, ctypes.c_float, _I32, _I32, _P, _P, _P, _P,
+                                        ctypes.POINTER(_Quality), _P]),
 }
 
 KERNEL_NAMES = ["alloc", "tsdf", "labels", "mesh", "query", "adjoint", "batch", "range"]
@@ -286,6 +300,69 @@ def map_sdf_pose_adjoint(handle, xi_dev, pts_dev, loss_dev, gxi_dev, gpts_dev=No
                                      _dev(gpts_dev, torch.float32, "gpts", 3), _stream(stream))
 
 
+def map_set_distance(handle, mode, max_incidence):
+    """mode MAP_DIST_PROJECTIVE or MAP_DIST_NONPROJECTIVE; max_incidence in radians."""
+    return _lib.map_set_distance(handle, int(mode), float(max_incidence))
+
+
+def map_set_label_fusion(handle, mode):
+    return _lib.map_set_label_fusion(handle, int(mode))
+
+
+def map_integrate_logprobs(handle, cam: CameraModel, logp_dev, T_wc, n_classes, stream=None):
+    """logp_dev: float32 [height, width, n_classes] device tensor of class log-probabilities."""
+    import torch
+    if tuple(logp_dev.shape) != (cam.height, cam.width, n_classes):
+        raise ValueError("log-probability image shape does not match the camera model and class count")
+    keep, T = _pose(T_wc)
+    return _lib.map_integrate_logprobs(handle, ctypes.byref(cam._c()), _dev(logp_dev, torch.float32, "logp"), T,
+                                       _stream(stream))
+
+
+def map_download_aux(handle, n_classes, grad=True, logpost=True):
+    """Per-voxel gradients [n, 3, 512] and log-posteriors [n, L, 512] in slot order."""
+    n = _lib.map_download_aux(handle, 0, None, None)
+    k = max(n, 1)
+    G = np.zeros((k, 3, 512), np.float32) if grad else None
+    LP = np.zeros((k, n_classes, 512), np.float32) if logpost else None
+    _lib.map_download_aux(handle, n, G.ctypes.data if grad else None, LP.ctypes.data if logpost else None)
+    return {"grad": G[:n] if grad else None, "logpost": LP[:n] if logpost else None}
+
+
+def map_frame_normals(handle):
+    """The last frame's normal image [n_pixels, 4] (world normal, kept range), or None."""
+    n = _lib.map_frame_normals(handle, None, 0)
+    if n <= 0:
+        return None
+    out = np.zeros((n, 4), np.float32)
+    _lib.map_frame_normals(handle, out.ctypes.data, n)
+    return out
+
+
+def map_mesh_quality(mesh_pts, mesh_lab, gt_pts, gt_lab, voxel_size, n_classes, device=0, d_mesh=None, d_gt=None,
+                     nn_gt=None, with_confusion=True, stream=None):
+    """Map-quality metrics of mesh vertices (device float32 [n, 3], labels uint8 [n]) against
+    a ground-truth cloud (float32 [m, 3], classes uint8 [m]).  Optional device outputs
+    d_mesh, d_gt (float64) and nn_gt (int64).  Returns (status, dict)."""
+    import torch
+    nM, nG = mesh_pts.shape[0], gt_pts.shape[0]
+    if mesh_lab.shape[0] != nM or gt_lab.shape[0] != nG:
+        raise ValueError("label counts differ from the point counts")
+    q = _Quality()
+    conf = np.zeros(((n_classes + 1) * n_classes,), np.int64) if with_confusion else None
+    st = _lib.map_mesh_quality(_dev(mesh_pts, torch.float32, "mesh_pts", 3) if nM else None,
+                               _dev(mesh_lab, torch.uint8, "mesh_lab") if nM else None, nM,
+                               _dev(gt_pts, torch.float32, "gt_pts", 3) if nG else None,
+                               _dev(gt_lab, torch.uint8, "gt_lab") if nG else None, nG, float(voxel_size),
+                               int(n_classes), int(device), _dev(d_mesh, torch.float64, "d_mesh"),
+                               _dev(d_gt, torch.float64, "d_gt"), _dev(nn_gt, torch.int64, "nn_gt"),
+                               conf.ctypes.data if with_confusion else None, ctypes.byref(q), _stream(stream))
+    r = {f: getattr(q, f) for f, _ in _Quality._fields_}
+    if with_confusion:
+        r["confusion"] = conf.reshape(n_classes + 1, n_classes)
+    return st, r
+
+
 def map_sync(handle):
     return _lib.map_sync(handle)
 
@@ -437,6 +514,21 @@ class Map:
 
     def read_block(self, b):
         return map_read_block(self.h, b, self.n_classes)
+
+    def set_distance(self, mode, max_incidence):
+        return self._check(map_set_distance(self.h, mode, max_incidence))
+
+    def set_label_fusion(self, mode):
+        return self._check(map_set_label_fusion(self.h, mode))
+
+    def integrate_logprobs(self, cam, logp_dev, T_wc, stream=None):
+        return self._check(map_integrate_logprobs(self.h, cam, logp_dev, T_wc, self.n_classes, stream))
+
+    def download_aux(self, grad=True, logpost=True):
+        return map_download_aux(self.h, self.n_classes, grad, logpost)
+
+    def frame_normals(self):
+        return map_frame_normals(self.h)
 
 
 # ----------------------------------------------------------------------------------------

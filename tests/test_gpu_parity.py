@@ -347,15 +347,27 @@ def test_pose_adjoint_full_size(torch_dev):
     m.sdf_pose_adjoint(X, P, loss2, gxi2, None)
     assert torch.equal(loss, loss2) and torch.equal(gxi, gxi2)  # fixed-order reduction
     L, G, GP = loss.cpu().numpy(), gxi.cpu().numpy(), gp.cpu().numpy()
-    # every pose: loss and dL/dxi against the fp64 oracle
+    # every pose: loss and dL/dxi against the fp64 oracle, over the points whose transformed
+    # position is more than 1e-3 voxel from every cell face (elsewhere the fp32 and fp64
+    # transforms can take different cells, and the loss jumps by up to tau^2 where a point's
+    # eight corners change validity); both sides see the same subset
     OL, OG, OGP, MARGIN = om.pose_adjoint(xi.astype(np.float64), np.broadcast_to(pts, (B, N, 3)))
+    n_kept = 0
     for b in range(B):
-        g_norm = np.linalg.norm(OGP[b], axis=1)
+        keep = MARGIN[b] > 1e-3
+        sub = np.ascontiguousarray(pts[keep])
+        n_kept += len(sub)
+        ol, og, ogp, _ = om.pose_adjoint(xi[b:b + 1].astype(np.float64), sub[None])
+        ls, gs = torch.empty(1, device=dev), torch.empty(1, 6, device=dev)
+        m.sdf_pose_adjoint(torch.from_numpy(xi[b:b + 1]).to(dev), torch.from_numpy(sub[None]).to(dev), ls, gs, None)
+        ls, gs = float(ls.cpu()[0]), gs.cpu().numpy()[0]
+        g_norm = np.linalg.norm(ogp[0], axis=1)
         scale_t = g_norm.sum()
-        scale_w = (np.linalg.norm(pts, axis=1) * g_norm).sum()
-        assert abs(L[b] - OL[b]) <= 1e-4 * OL[b] + 1e-3 * w.trunc ** 2, (b, L[b], OL[b])
-        assert np.all(np.abs(G[b, :3] - OG[b, :3]) <= 1e-4 * scale_t + 1e-3), (b, G[b], OG[b])
-        assert np.all(np.abs(G[b, 3:] - OG[b, 3:]) <= 1e-4 * scale_w + 1e-3), (b, G[b], OG[b])
+        scale_w = (np.linalg.norm(sub, axis=1) * g_norm).sum()
+        assert abs(ls - ol[0]) <= 1e-4 * ol[0] + 1e-3 * w.trunc ** 2, (b, ls, ol[0])
+        assert np.all(np.abs(gs[:3] - og[0, :3]) <= 1e-4 * scale_t + 1e-3), (b, gs, og[0])
+        assert np.all(np.abs(gs[3:] - og[0, 3:]) <= 1e-4 * scale_w + 1e-3), (b, gs, og[0])
+    assert n_kept > 0.99 * B * N
     for b in (0, 17, 40, 63):
         ogp, margin = OGP[b:b + 1], MARGIN[b:b + 1]
         g_norm = np.linalg.norm(ogp[0], axis=1)
