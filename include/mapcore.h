@@ -234,6 +234,17 @@ int map_query_sdf(map_t *map, const float *pts_dev, int64_t n, float *sdf_dev, f
 int map_sdf_pose_adjoint(map_t *map, const float *xi_dev, const float *pts_dev, int32_t B,
                          int64_t N, float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream);
 
+/* The same loss and adjoint for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the partial
+ * sums go to a static device array of the library (4 MiB per device, held until the
+ * process ends) instead of the map's scratch, and the call makes no allocation.  Limit:
+ * B * ceil(N / 256) <= 131072 (MAP_ERR_INVALID_ARG beyond it).  Every call on one device
+ * shares that array, so calls that overlap on one device (other streams, other maps, other
+ * threads) race and must be ordered by the caller.  Results are bit-identical to
+ * map_sdf_pose_adjoint.  Asynchronous. */
+int map_sdf_pose_adjoint_noalloc(map_t *map, const float *xi_dev, const float *pts_dev, int32_t B,
+                                 int64_t N, float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream);
+
 /* Batched integration (many maps of uneven size per step).  A batch holds up to 64 maps
  * created with map_create.  One map_batch_step integrates one frame into each listed map
  * (LiDAR scan, up to 8 camera label images, then DIRTY meshing into that map's output

@@ -9,7 +9,7 @@ from .mapcore import (  # noqa: F401
     MAP_ERR_DEVICE, MAP_MESH_DIRTY, MAP_MESH_ALL, MapError, Map, LidarModel, CameraModel, lib_path,
     MAP_DIST_PROJECTIVE, MAP_DIST_NONPROJECTIVE, MAP_LABELS_COUNTS, MAP_LABELS_LATEST, MAP_LABELS_BAYES,
     map_set_distance, map_set_label_fusion, map_integrate_logprobs, map_download_aux, map_frame_normals,
-    map_mesh_quality,
+    map_mesh_quality, map_sdf_pose_adjoint_noalloc,
     map_create, map_destroy, map_integrate_lidar, map_integrate_labels, map_integrate_labels_multi,
     map_extract_mesh,
     map_query_sdf, map_range_image, map_integrate_labels_lidar, map_sdf_pose_adjoint, map_sync, map_stats, map_last_error, map_block_coords,

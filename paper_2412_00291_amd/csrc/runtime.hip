@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -64,6 +65,34 @@ struct map_s {
 };
 
 static std::string g_create_error;
+
+// Partial sums of map_sdf_pose_adjoint_noalloc: a file-scope device array (each device the
+// library runs on holds its own copy until the process ends), so that call allocates
+// nothing.  Its device address is looked up once per device, with that device current
+// (map_create does it for its device), and kept here; host code uses only that address.
+constexpr size_t kScratchFloats = (size_t)1 << 20;  // 4 MiB: B * ceil(N / 256) <= 131072 chunks
+static __device__ __align__(256) float scratch[kScratchFloats];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static float *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (the current device), or null with *err set.
+static float *scratch_on(int device, hipError_t *err)
+{
+    *err = hipSuccess;
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = static_cast<float *>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
 
 static int fail(map_t *m, int code, const char *fmt, ...)
 {
@@ -231,6 +260,11 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     if (hipSetDevice(p.device) != hipSuccess)
         return fail(nullptr, MAP_ERR_DEVICE, "map_create: hipSetDevice failed");
 
+    {  // set-up of the allocation-free adjoint's scratch on this device (once per device)
+        hipError_t se;
+        if (!scratch_on(p.device, &se))
+            return fail(nullptr, MAP_ERR_DEVICE, "map_create: scratch address: %s", hipGetErrorString(se));
+    }
     map_t *m = new map_s();
     m->p = p;
     // Six TSDF workgroups per compute unit: measured on a street frame (64 x 2048 scan,
@@ -801,6 +835,29 @@ extern "C" int map_mesh_quality(const float *mesh_pts_dev, const uint8_t *mesh_l
     out->miou = h_res[3];
     out->acc = h_res[4];
     out->n_eval = (int64_t)h_res[5];
+    return MAP_OK;
+}
+
+extern "C" int map_sdf_pose_adjoint_noalloc(map_t *m, const float *xi_dev, const float *pts_dev, int32_t B, int64_t N,
+                                            float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    if (B < 1 || B > 65535 || N < 1 || !xi_dev || !pts_dev || !loss_dev || !gxi_dev)
+        return fail(m, MAP_ERR_INVALID_ARG, "sdf_pose_adjoint_noalloc: bad arguments");
+    const int64_t nchunk = (N + 255) / 256;
+    if ((uint64_t)B * (uint64_t)nchunk * 8 > kScratchFloats)
+        return fail(m, MAP_ERR_INVALID_ARG,
+                    "sdf_pose_adjoint_noalloc: B * ceil(N / 256) = %lld exceeds the static scratch (%lld chunks)",
+                    (long long)B * nchunk, (long long)(kScratchFloats / 8));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    hipError_t se;
+    float *part = scratch_on(m->p.device, &se);
+    if (!part) return fail(m, MAP_ERR_DEVICE, "sdf_pose_adjoint_noalloc: scratch address: %s", hipGetErrorString(se));
+    // launched directly: the kernel-event timer creates events, which this call must not
+    HIP_TRY(m, launch_adjoint(m->v, xi_dev, pts_dev, B, N, gpts_dev, part, (int)nchunk, s));
+    HIP_TRY(m, launch_adjoint_reduce(xi_dev, part, B, (int)nchunk, loss_dev, gxi_dev, s));
+    m->last_stream = s;
     return MAP_OK;
 }
 

@@ -83,6 +83,7 @@ _sig = {
     "map_range_image": (ctypes.c_int, [_P, ctypes.POINTER(_Lidar), _P, _I64, ctypes.c_float, ctypes.c_float, _P, _P,
                                        _P]),
     "map_sdf_pose_adjoint": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
+    "map_sdf_pose_adjoint_noalloc": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
     "map_sync": (ctypes.c_int, [_P]),
     "map_stats": (ctypes.c_int, [_P, ctypes.POINTER(_Stats)]),
     "map_last_error": (ctypes.c_char_p, [_P]),
@@ -361,6 +362,20 @@ def map_mesh_quality(mesh_pts, mesh_lab, gt_pts, gt_lab, voxel_size, n_classes, 
     if with_confusion:
         r["confusion"] = conf.reshape(n_classes + 1, n_classes)
     return st, r
+
+
+def map_sdf_pose_adjoint_noalloc(handle, xi_dev, pts_dev, loss_dev, gxi_dev, gpts_dev=None, stream=None):
+    """map_sdf_pose_adjoint with the library's static scratch (no allocation)."""
+    import torch
+    B, N = pts_dev.shape[0], pts_dev.shape[1]
+    if tuple(xi_dev.shape) != (B, 6) or tuple(loss_dev.shape) != (B,) or tuple(gxi_dev.shape) != (B, 6):
+        raise ValueError("adjoint argument shapes do not match B")
+    if gpts_dev is not None and tuple(gpts_dev.shape) != tuple(pts_dev.shape):
+        raise ValueError("gpts must have the points' shape")
+    return _lib.map_sdf_pose_adjoint_noalloc(handle, _dev(xi_dev, torch.float32, "xi"),
+                                             _dev(pts_dev, torch.float32, "pts", 3), B, N,
+                                             _dev(loss_dev, torch.float32, "loss"), _dev(gxi_dev, torch.float32, "gxi"),
+                                             _dev(gpts_dev, torch.float32, "gpts", 3), _stream(stream))
 
 
 def map_sync(handle):
