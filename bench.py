@@ -181,9 +181,9 @@ def measured_traffic(kernel, sched):
     return rec.get("bytes_per_launch", {}).get(kernel)
 
 
-def cpu_baseline(w, frames, budget_s):
+def _cpu_run(w, frames, budget_s, variant):
     import oracle
-    om = oracle.OracleMap(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    om = oracle.OracleMap(w.voxel, w.trunc, w.n_classes, w.max_blocks, variant=variant)
     U = 0
     t_total = 0.0
     n = 0
@@ -198,10 +198,24 @@ def cpu_baseline(w, frames, budget_s):
         n += 1
         if t_total >= budget_s:
             break
-    return {"value": U / t_total, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"street frames 0-{n - 1} of the same sequence, whole path per frame "
-                      f"(scan + 4 label images + dirty mesh), single-threaded plain C",
-            "ms_per_frame": 1e3 * t_total / n, "frames": n,
+    om.close()
+    return U / t_total, 1e3 * t_total / n, n
+
+
+def cpu_baseline(w, frames, budget_s):
+    """The oracle on this host's cores, whole path per frame, on the first frames of the same
+    sequence: its OpenMP build (every host thread; loops over rows, touched blocks and meshed
+    blocks in parallel, identical results) and its plain single-threaded build."""
+    import oracle
+    threads = oracle.threads("omp")
+    v_omp, ms_omp, n_omp = _cpu_run(w, frames, budget_s, "omp")
+    v_one, ms_one, n_one = _cpu_run(w, frames, budget_s, "plain")
+    return {"value": v_omp, "unit": "voxel-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"street frames 0-{n_omp - 1} of the same sequence, whole path per frame "
+                      f"(scan + 4 label images + dirty mesh), OpenMP build on {threads} threads",
+            "ms_per_frame": ms_omp, "frames": n_omp,
+            "single_thread": {"value": v_one, "unit": "voxel-updates/s", "cores": 1, "ms_per_frame": ms_one,
+                              "frames": n_one, "sample": f"street frames 0-{n_one - 1}, plain build"},
             "cpu": _cpu_model(), "host_threads_available": len(os.sched_getaffinity(0))}
 
 
