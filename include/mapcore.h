@@ -96,10 +96,15 @@ void map_destroy(map_t *map);
  *     psi < -tau are skipped; w = min((psi + tau) / (2 tau), 1);
  *     D <- (W D + w min(psi, tau)) / (W + w), W <- W + w.
  * The touched blocks and their lower neighbours join the dirty set.
- * Asynchronous: returns after enqueueing.  If the frame would allocate more than
- * max_blocks in total, the frame is rejected on the device with the map unchanged (and
- * later label calls are no-ops until the next accepted frame); MAP_ERR_CAPACITY is then
- * returned by the next map_sync or map_stats. */
+ * Asynchronous: returns after enqueueing the allocation pass, which also copies the range
+ * image into the map.  The TSDF pass is enqueued by the map's next call, on this call's
+ * stream: fused with the camera label fusion when that call is map_integrate_labels(_multi)
+ * on the same stream (camera labels and counts or latest-label fusion), before anything
+ * else otherwise; so range_dev need only stay valid until this call's work on `stream`
+ * completes, as for any call.  If the frame would allocate more than max_blocks in total,
+ * the frame is rejected on the device with the map unchanged (and later label calls are
+ * no-ops until the next accepted frame); MAP_ERR_CAPACITY is then returned by the next
+ * map_sync or map_stats. */
 int map_integrate_lidar(map_t *map, const lidar_model *lidar, const float *range_dev,
                         const float T_wl[16], void *stream);
 
@@ -305,7 +310,8 @@ const char *map_last_error(const map_t *map);
 #define MAP_K_ADJOINT 5    /* pose / point adjoint (both of its launches) */
 #define MAP_K_BATCH 6      /* batched multi-map step */
 #define MAP_K_RANGE 7      /* point cloud to depth and height images (both launches) */
-#define MAP_KERNEL_COUNT 8
+#define MAP_K_TSDF_LABELS 8 /* the TSDF launch with the frame's camera label fusion fused in */
+#define MAP_KERNEL_COUNT 9
 int map_profile(map_t *map, uint32_t mask);
 int map_profile_read(map_t *map, double *total_ms, int64_t *launches);
 

@@ -325,7 +325,7 @@ __device__ __forceinline__ float4 pixel_normal(const LidarLUT &L, const Pose &T,
 // blocks exactly as the half-open cells require.  With the non-projective distance (kNP)
 // the pixel's normal and point filter come first (stored in the frame's normal image),
 // and the kept return is the one walked.
-template <bool kNP = false>
+template <bool kNP = false, bool kCopy = false>
 __device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapView &m, const FrameView &f,
                                             const LidarLUT &L, const Pose &T, const float *__restrict__ range,
                                             int pix, float cos_inc = 0.0f)
@@ -338,6 +338,7 @@ __device__ __forceinline__ void alloc_pixel(unsigned long long *lk, const MapVie
         r = nr.w;
     } else {
         r = range[pix];
+        if (kCopy) f.rcopy[pix] = r;  // the frame's own copy, read by the TSDF launch
     }
     const float ce = L.ce[k], se = L.se[k], cp = L.cp[c], sp = L.sp[c];
     // the table reads wait here with the return (else the compiler moves them past the
@@ -717,7 +718,8 @@ __device__ __forceinline__ bool tsdf_update_np(const MapView &m, const LidarLUT 
 template <int kWidth, bool kNP = false>
 __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const FrameView &f, const LidarLUT &L,
                                                          const Pose &T, const float *__restrict__ range, int e,
-                                                         unsigned long long key, int slot, int rank)
+                                                         unsigned long long key, int slot, int rank,
+                                                         unsigned long long *s_band = nullptr)
 {
     static_assert(kWidth % 64 == 0, "a wavefront covers whole z slices");
     constexpr int kV = kBlockVoxels / kWidth;
@@ -766,6 +768,7 @@ __device__ __forceinline__ unsigned long long tsdf_block(const MapView &m, const
             f.band[(size_t)e * 8 + (li >> 6)] = bits;
             m.vmask[(size_t)slot * 16 + (li >> 6)] = sg;
             m.vmask[(size_t)slot * 16 + 8 + (li >> 6)] = ob;
+            if (s_band) s_band[li >> 6] = bits;  // the block's band words for fused label fusion
         }
     }
     return upd;
@@ -796,12 +799,14 @@ __device__ __forceinline__ void close_frame(const MapView &m, const FrameState &
     c->overflow = 0;
 }
 
-// The last workgroup's part of closing a map's frame: wave 0 takes the update count and
-// clears the votes, then closes the frame.
-__device__ __forceinline__ void close_frame_wave(const MapView &m, const FrameState &fs)
+// The last workgroup's part of closing a map's frame: wave 0 takes the update count (and,
+// with clear_votes, clears the label votes of the previous frame; the per-map path clears
+// them in its allocation launch instead, so a TSDF launch that also fuses labels keeps its
+// own), then closes the frame.
+__device__ __forceinline__ void close_frame_wave(const MapView &m, const FrameState &fs, bool clear_votes = true)
 {
     const unsigned long long upd = spread_take_wave(m.sync->updates);
-    (void)spread_take_wave(m.sync->votes);
+    if (clear_votes) (void)spread_take_wave(m.sync->votes);
     if ((threadIdx.x & 63) == 0) close_frame(m, fs, upd);
 }
 
@@ -845,6 +850,19 @@ __device__ __forceinline__ BandWords band_words(const FrameView &f, int e)
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         b.w[k] = f.band[(size_t)e * 8 + k];
+        b.pre[k + 1] = b.pre[k] + __popcll(b.w[k]);
+    }
+    return b;
+}
+
+// The same from a block's eight band words in LDS.
+__device__ __forceinline__ BandWords band_words_lds(const unsigned long long *w)
+{
+    BandWords b;
+    b.pre[0] = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        b.w[k] = w[k];
         b.pre[k + 1] = b.pre[k] + __popcll(b.w[k]);
     }
     return b;

@@ -100,12 +100,26 @@ struct MapView {
 
 constexpr int kMaxMeshGrid = 4096;  // workgroups of a meshing pass (and of a batched phase)
 
+// A block with triangles, recorded by the counting pass of a per-map extraction for the
+// emitting pass: its coordinates (x, y, z) and pool slot (w), and the slots of b + e,
+// e in {0,1}^3 (-1 when absent).
+struct __align__(16) MeshRec {
+    int4 bc;
+    int nb[8];
+};
+
 // Scratch of one extraction: per-workgroup triangle and block counts of the counting
 // pass, and the output offsets of the emitting pass (per map of a batch: [grid][maps]).
+// Per-map extractions also keep the counting pass's records: counting workgroup c writes
+// its blocks with triangles, in its candidate order, to rec[c * rec_cap ...], and their
+// number to wg_nz[c].
 struct MeshScan {
     long long *wg_tris;
     int32_t *wg_blocks;
     long long *wg_off;
+    MeshRec *rec;
+    int32_t *wg_nz;
+    int32_t rec_cap;
 };
 
 // An extraction's totals, written by the scan kernel straight into host-mapped pinned
@@ -124,6 +138,8 @@ struct FrameView {
     int32_t *tk_rank;           // [tk_cap] rank among new blocks
     int32_t *tk_fslot;          // [tk_cap] frame-set slot (cleared at frame end)
     unsigned long long *band;   // [tk_cap][8] band bits (|psi| <= tau) per voxel
+    float *rcopy;               // [rows * cols] the scan's range image, copied by the allocation
+                                // launch (the TSDF launch, enqueued later, reads this copy)
     float4 *nimg;               // [rows * cols] non-projective distance: the scan's world-frame
                                 // normals (xyz) and kept ranges (w, 0 where the point filter
                                 // drops the return); null in projective mode
@@ -260,8 +276,11 @@ constexpr int kLabelCounts = 0, kLabelLatest = 1, kLabelBayes = 2;
 
 hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
                         const float *range, int dist_mode, float cos_inc, hipStream_t s);
+// The TSDF launch, optionally fused with the label fusion of up to kMaxCams cameras
+// (label_mode kLabelCounts or kLabelLatest; cams.n == 0: no labels).
 hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                       const float *range, uint32_t frame_id, int schedule, int grid, int dist_mode, hipStream_t s);
+                       const float *range, uint32_t frame_id, int schedule, int grid, int dist_mode,
+                       const CameraSet &cams, int label_mode, hipStream_t s);
 hipError_t launch_labels(const MapView &m, const FrameView &f, const CameraSet &cams, int schedule, int grid,
                          int label_mode, hipStream_t s);
 hipError_t launch_logprobs(const MapView &m, const FrameView &f, const Camera &cam, const Pose &T, const float *logp,

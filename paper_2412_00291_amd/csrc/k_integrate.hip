@@ -55,10 +55,13 @@ __global__ __launch_bounds__(kThreads) void k_alloc(MapView m, FrameView f, Lida
     __shared__ unsigned long long lk[kLdsKeys];
     __shared__ int s_tmp[kThreads / 64];
     __shared__ unsigned long long s_base;
+    // the frame starts: the previous frame's label votes are cleared here (its label launches
+    // have completed), so the TSDF launch, which may fuse this frame's labels, keeps its own
+    if (blockIdx.x == 0 && threadIdx.x < 64) (void)spread_take_wave(m.sync->votes);
     for (int i = threadIdx.x; i < kLdsKeys; i += kThreads) lk[i] = kEmpty;
     __syncthreads();
     const int pix = blockIdx.x * kThreads + threadIdx.x;
-    if (pix < L.rows * L.cols) alloc_pixel<kNP>(lk, m, f, L, T, range, pix, cos_inc);
+    if (pix < L.rows * L.cols) alloc_pixel<kNP, true>(lk, m, f, L, T, range, pix, cos_inc);
     __syncthreads();
     alloc_flush(lk, s_tmp, &s_base, m, f);
 }
@@ -87,9 +90,40 @@ hipError_t launch_alloc(const MapView &m, const FrameView &f, const LidarLUT &lu
 // workgroup copies them (cols + rows + 1 pairs, 17 KiB for 2048 columns) into dynamic LDS
 // when the launch provides it (kLdsLut), so that the range image is the voxel's only
 // global read on the way to its update.
-template <int kSched, bool kLdsLut, bool kNP>
+// kLab: label fusion of the frame's camera label images fused into the pass (0 none, 1 vote
+// counts, 2 latest label): the band words of a chunk's blocks are gathered in LDS while
+// the blocks are updated, and after the chunk's updates the worker takes all of their band
+// voxels as one flat list and votes them exactly as the label kernel would (the votes of
+// a voxel depend only on that voxel), so a chunk's label reads are one latency chain.
+template <int kN>
+struct ChunkBand {
+    unsigned long long w[kN][8];  // band words of the chunk's blocks
+    int pre[kN][9];               // prefix of each block's word popcounts
+    int epre[kN + 1];             // prefix of the blocks' band voxels
+    int slot[kN];
+    int3 bc[kN];
+};
+
+// Band voxel t (< the chunk's total) of the chunk: block j, voxel li.
+template <int kN>
+__device__ __forceinline__ void chunk_band_voxel(const ChunkBand<kN> &g, int n, int t, int &j, int &li)
+{
+    int lo = 0, hi = n - 1;  // last block whose prefix is <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.epre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    j = lo;
+    const int local = t - g.epre[j];
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) k += g.pre[j][i] <= local ? 1 : 0;
+    li = band_bit(g.w[j][k], k, local - g.pre[j][k]);
+}
+template <int kSched, bool kLdsLut, bool kNP, int kLab>
 __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, LidarLUT L, Pose T,
-                                                  const float *__restrict__ range, uint32_t frame_id)
+                                                  const float *__restrict__ range, uint32_t frame_id, CameraSet cs)
 {
     constexpr int kWidth = kSched == 0 ? kThreads : 64;
     constexpr int kChunk = kWidth / 8;  // entries per chunk: eight marking lanes each
@@ -97,13 +131,16 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
     __shared__ int s_slot[kThreads / 8];
     __shared__ int s_last;
     __shared__ unsigned long long s_sum[kThreads / 64];
+    __shared__ unsigned long long s_vsum[kThreads / 64];
+    __shared__ ChunkBand<kLab ? kChunk : 1> s_cb[kLab ? (kSched == 0 ? 1 : kThreads / 64) : 1];
     if (kLdsLut) stage_lut(L, s_lut);
     const FrameState fs = frame_state(m, f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int first = kSched == 0 ? (int)blockIdx.x : (int)blockIdx.x * (kThreads / 64) + wave;
     const int stride = kSched == 0 ? (int)gridDim.x : (int)gridDim.x * (kThreads / 64);
-    unsigned long long my_updates = 0;
+    unsigned long long my_updates = 0, my_votes = 0;
+    auto &cb = s_cb[kLab && kSched != 0 ? wave : 0];
     for (int base = first; base < fs.n_list; base += kChunk * stride) {
         int my_slot = -1;  // lane i < kChunk commits entry base + i * stride
         const int ec = base + rank * stride;
@@ -117,7 +154,46 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
                 const int e = base + j * stride;
                 if (e >= fs.n_list) break;
                 const int slot = kSched == 0 ? s_slot[j] : __shfl(my_slot, j, 64);
-                my_updates += tsdf_block<kWidth, kNP>(m, f, L, T, range, e, f.tk_key[e], slot, rank);
+                const unsigned long long key = f.tk_key[e];
+                my_updates += tsdf_block<kWidth, kNP>(m, f, L, T, range, e, key, slot, rank,
+                                                       kLab ? cb.w[j] : nullptr);
+                if (kLab && rank == 0) {
+                    cb.slot[j] = slot;
+                    cb.bc[j] = unpack_key(key);
+                }
+            }
+            if (kLab) {  // the chunk's band voxels as one flat list
+                const int nE = min(kChunk, (fs.n_list - base + stride - 1) / stride);
+                if (kSched == 0) __syncthreads();
+                else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (rank < nE) {
+                    int p = 0;
+                    cb.pre[rank][0] = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        p += __popcll(cb.w[rank][k]);
+                        cb.pre[rank][k + 1] = p;
+                    }
+                }
+                if (kSched == 0) __syncthreads();
+                else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (rank == 0) {
+                    int p = 0;
+                    for (int j = 0; j < nE; ++j) {
+                        cb.epre[j] = p;
+                        p += cb.pre[j][8];
+                    }
+                    cb.epre[nE] = p;
+                }
+                if (kSched == 0) __syncthreads();
+                else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll 1
+                for (int t = rank; t < cb.epre[nE]; t += kWidth) {
+                    int j, li;
+                    chunk_band_voxel(cb, nE, t, j, li);
+                    my_votes += kLab == 2 ? label_voxel_latest(m, cs, cb.slot[j], cb.bc[j], li)
+                                          : label_voxel(m, cs, cb.slot[j], cb.bc[j], li);
+                }
             }
             // dirty marks last: nothing above waits for their hash probes
             const int i = rank >> 3;  // lane r marks neighbour r % 8 of entry r / 8
@@ -131,41 +207,67 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
         if (kSched == 0) __syncthreads();  // s_slot is rewritten by the next chunk
     }
     const unsigned long long w = wave_sum_u64(my_updates);
-    if (lane == 0) s_sum[wave] = w;
+    const unsigned long long wv = kLab ? wave_sum_u64(my_votes) : 0ull;
+    if (lane == 0) {
+        s_sum[wave] = w;
+        s_vsum[wave] = wv;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int i = 0; i < kThreads / 64; ++i) t += s_sum[i];
+        unsigned long long t = 0, tv = 0;
+        for (int i = 0; i < kThreads / 64; ++i) {
+            t += s_sum[i];
+            tv += s_vsum[i];
+        }
         if (t) spread_add(m.sync->updates, t);
+        if (kLab && tv) spread_add(m.sync->votes, tv);
         s_last = ticket_arrive(m.sync->tsdf);
     }
     __syncthreads();
-    if (s_last && wave == 0) close_frame_wave(m, fs);
+    if (s_last && wave == 0) close_frame_wave(m, fs, false);
 }
 
-template <bool kNP>
+template <bool kNP, int kLab>
 static void launch_tsdf_t(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                          const float *range, uint32_t frame_id, int schedule, int grid, hipStream_t s)
+                          const float *range, uint32_t frame_id, int schedule, int grid, const CameraSet &cs,
+                          hipStream_t s)
 {
     const size_t lds = ((size_t)lut.cols + lut.rows + 1) * sizeof(float2);
     if (lds <= kMaxLdsLut) {
         if (schedule == 0)
-            hipLaunchKernelGGL((k_tsdf<0, true, kNP>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<0, true, kNP, kLab>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range,
+                               frame_id, cs);
         else
-            hipLaunchKernelGGL((k_tsdf<1, true, kNP>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<1, true, kNP, kLab>), dim3(grid), dim3(kThreads), lds, s, m, f, lut, T, range,
+                               frame_id, cs);
     } else {
         if (schedule == 0)
-            hipLaunchKernelGGL((k_tsdf<0, false, kNP>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<0, false, kNP, kLab>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range,
+                               frame_id, cs);
         else
-            hipLaunchKernelGGL((k_tsdf<1, false, kNP>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range, frame_id);
+            hipLaunchKernelGGL((k_tsdf<1, false, kNP, kLab>), dim3(grid), dim3(kThreads), 0, s, m, f, lut, T, range,
+                               frame_id, cs);
     }
 }
 
-hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
-                       const float *range, uint32_t frame_id, int schedule, int grid, int dist_mode, hipStream_t s)
+template <bool kNP>
+static void launch_tsdf_l(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                          const float *range, uint32_t frame_id, int schedule, int grid, const CameraSet &cs,
+                          int label_mode, hipStream_t s)
 {
-    if (dist_mode == kDistNonProjective) launch_tsdf_t<true>(m, f, lut, T, range, frame_id, schedule, grid, s);
-    else launch_tsdf_t<false>(m, f, lut, T, range, frame_id, schedule, grid, s);
+    if (cs.n == 0) launch_tsdf_t<kNP, 0>(m, f, lut, T, range, frame_id, schedule, grid, cs, s);
+    else if (label_mode == kLabelLatest) launch_tsdf_t<kNP, 2>(m, f, lut, T, range, frame_id, schedule, grid, cs, s);
+    else launch_tsdf_t<kNP, 1>(m, f, lut, T, range, frame_id, schedule, grid, cs, s);
+}
+
+hipError_t launch_tsdf(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,
+                       const float *range, uint32_t frame_id, int schedule, int grid, int dist_mode,
+                       const CameraSet &cams, int label_mode, hipStream_t s)
+{
+    if (dist_mode == kDistNonProjective)
+        launch_tsdf_l<true>(m, f, lut, T, range, frame_id, schedule, grid, cams, label_mode, s);
+    else
+        launch_tsdf_l<false>(m, f, lut, T, range, frame_id, schedule, grid, cams, label_mode, s);
     return hipGetLastError();
 }
 

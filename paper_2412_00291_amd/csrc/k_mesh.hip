@@ -1,8 +1,8 @@
 // Marching cubes over the dirty (or all) blocks of one map, in two launches: count
-// triangles per workgroup, then emit, each emitting workgroup at the sum of the counts
-// before it (workgroup 0 also does the extraction's bookkeeping and the host report).
-// Both passes take the same candidate blocks in the same order (see mesh_device.h), so
-// the output is compact.
+// triangles per workgroup and record the blocks with triangles, then emit from those
+// records, each emitting workgroup at the sum of the counts before it (workgroup 0 also
+// does the extraction's bookkeeping and the host report).  The emitting workgroup takes
+// its counting workgroups' records in their order, so the output is compact.
 #include "mesh_device.h"
 
 namespace mc {
@@ -14,7 +14,8 @@ __global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, Me
     const uint32_t epoch = c->dirty_epoch;
     long long tris;
     int blocks;
-    mesh_count_wg(m, mode != 0, epoch, c->pool_used, S, &tris, &blocks);
+    mesh_count_wg(m, mode != 0, epoch, c->pool_used, S, &tris, &blocks, scan.rec + (size_t)blockIdx.x * scan.rec_cap,
+                  scan.wg_nz + blockIdx.x, scan.rec_cap);
     if (threadIdx.x == 0) {
         scan.wg_tris[blockIdx.x] = tris;
         scan.wg_blocks[blockIdx.x] = blocks;
@@ -31,8 +32,7 @@ __global__ __launch_bounds__(kThreads) void k_mesh_emit(MapView m, int mode, Mes
     __shared__ long long s_red[3 * (kThreads / 64)];
     const TableRegs tab = mesh_tables_load<true>();  // in flight with the counts
     const long long base = mesh_emit_base(m, mode, scan.wg_tris, scan.wg_blocks, g_count, out.cap, report, s_red);
-    const Counters *c = m.ctr;
-    mesh_emit_wg<kSched>(m, mode != 0, c->mesh_epoch, c->pool_used, base, out, S, st, tab);
+    mesh_emit_recs<kSched>(m, scan, g_count / (int)gridDim.x, base, out, S, st, tab);
 }
 
 MeshGrid mesh_grid(int schedule)
@@ -56,7 +56,8 @@ hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, i
 hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan,
                               MeshReport *report, int schedule, MeshGrid grid, hipStream_t s)
 {
-    if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
+    if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit ||
+        grid.count / grid.emit > kMaxRecParts)
         return hipErrorInvalidValue;
     if (schedule == 0)
         hipLaunchKernelGGL(k_mesh_emit<0>, dim3(grid.emit), dim3(kThreads), 0, s, m, mode, scan, out, grid.count, report);

@@ -34,6 +34,8 @@ struct HaloFull {
 // neighbour slots are looked up by the whole workgroup at once (eight lanes per block)
 // before any block of the batch is staged.
 constexpr int kMeshBatch = kThreads / 8;
+// Counting workgroups per emitting workgroup whose records an emitting workgroup reads.
+constexpr int kMaxRecParts = 16;
 
 // LDS of a meshing workgroup: the case tables (read per cube and per vertex, so they
 // are copied from global memory once per workgroup; the counting pass needs only the
@@ -53,6 +55,8 @@ struct __align__(16) MeshSmem {
     int mis[kMeshBatch];  // map of each batch entry (batched steps)
     int list[kThreads];
     int4 lbc[kEmit ? 1 : kThreads];  // counting pass: the candidates' coordinates
+    int bt[kMeshBatch];              // counting pass: triangles of each block of a batch
+    int rpre[kMaxRecParts + 1];      // emitting pass: prefix of its counting workgroups' records
     int wcnt[kThreads / 64];
     long long rcnt[kThreads / 64];
 };
@@ -443,14 +447,17 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
 }
 
 // Counting pass of one workgroup: triangles and blocks over its candidates, one
-// wavefront per block (halo rows from the voxel masks).
+// wavefront per block (halo rows from the voxel masks).  With rec (per-map extractions),
+// the blocks with triangles are recorded in candidate order (coordinates, slot, neighbour
+// slots) and their number is written to *nz, so the emitting pass reads them directly.
 __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32_t epoch, int nslots,
-                                              MeshSmem<1, HaloMask> &S, long long *tris, int *blocks)
+                                              MeshSmem<1, HaloMask> &S, long long *tris, int *blocks,
+                                              MeshRec *rec = nullptr, int32_t *nz = nullptr, int rec_cap = 0)
 {
     const TableRegs tab = mesh_tables_load<false>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     long long my_tris = 0;
-    int my_blocks = 0;
+    int my_blocks = 0, n_rec = 0;
     unsigned counts;
     for (int it = 0;; ++it) {
         const int n = mesh_candidates(m, all, epoch, nslots, it, false, S);
@@ -468,12 +475,31 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
                     m.mesh_cnt[S.nbs[j][0]] = (uint16_t)t;
                     my_tris += (long long)t;
                     my_blocks += 1;
+                    S.bt[j] = (int)t;
                 }
             }
-            __syncthreads();  // the batch's lookups are rewritten by the next batch
+            __syncthreads();
+            if (rec) {  // the batch's blocks with triangles, appended in batch order by wave 0
+                if (wave == 0) {
+                    const bool has = lane < nb && S.bt[lane] > 0;
+                    const unsigned long long bal = __ballot(has);
+                    const int at = n_rec + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (has && at < rec_cap) {
+                        int4 bc = S.lbc[j0 + lane];
+                        bc.w = S.list[j0 + lane];
+                        int4 *dst = reinterpret_cast<int4 *>(rec + at);
+                        dst[0] = bc;
+                        dst[1] = make_int4(S.nbs[lane][0], S.nbs[lane][1], S.nbs[lane][2], S.nbs[lane][3]);
+                        dst[2] = make_int4(S.nbs[lane][4], S.nbs[lane][5], S.nbs[lane][6], S.nbs[lane][7]);
+                    }
+                    n_rec += __popcll(bal);
+                }
+                __syncthreads();  // the batch's lookups are rewritten by the next batch
+            }
         }
         __syncthreads();  // the list is rewritten by the next iteration
     }
+    if (rec && threadIdx.x == 0) *nz = n_rec;
     // workgroup totals (kept on lane 0 of each wavefront)
     unsigned long long t = wave_sum_u64((unsigned long long)my_tris);
     unsigned long long b = wave_sum_u64((unsigned long long)my_blocks);
@@ -544,6 +570,77 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
             }
         }
         __syncthreads();
+    }
+}
+
+// Emitting pass of one per-map workgroup from the counting pass's records: the blocks of
+// counting workgroups w + j G (j < k) in that order, batch by batch (each batch's records
+// read at once into the lookup arrays), triangles from output index `base` on.  Rounds as
+// in mesh_emit_wg.
+template <int kSched>
+__device__ __forceinline__ void mesh_emit_recs(const MapView &m, const MeshScan &scan, int k, long long base,
+                                               const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st,
+                                               const TableRegs &tab)
+{
+    constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rank = kSched == 0 ? (int)threadIdx.x : lane;
+    const int worker = kSched == 0 ? 0 : wave;
+    const int G = (int)gridDim.x;
+    if (threadIdx.x == 0) {  // the record counts of this workgroup's counting workgroups
+        int p = 0;
+        S.rpre[0] = 0;
+        for (int j = 0; j < k; ++j) {
+            p += scan.wg_nz[blockIdx.x + j * G];
+            S.rpre[j + 1] = p;
+        }
+    }
+    mesh_tables_store<true>(S, tab);
+    __syncthreads();
+    const int total = S.rpre[k];
+    unsigned counts = 0;
+    long long carry = base;
+    for (int j0 = 0; j0 < total; j0 += kMeshBatch) {
+        const int nb = total - j0 < kMeshBatch ? total - j0 : kMeshBatch;
+        {  // eight lanes per record: lane e of record jb reads its neighbour slot e (and e = 0 the block)
+            const int jb = threadIdx.x >> 3, e = threadIdx.x & 7;
+            if (jb < nb) {
+                const int r = j0 + jb;
+                int j = 0;
+                for (int q = 1; q < k; ++q) j += S.rpre[q] <= r ? 1 : 0;
+                const MeshRec *src = scan.rec + (size_t)(blockIdx.x + j * G) * scan.rec_cap + (r - S.rpre[j]);
+                S.nbs[jb][e] = src->nb[e];
+                if (e == 0) S.bcs[jb] = src->bc;
+            }
+            __syncthreads();
+        }
+        for (int r = 0; r < nb; r += kPerRound) {
+            const int j = r + worker;
+            const bool has = j < nb;
+            int mine = 0;
+            if (kSched == 0) {
+                mesh_stage<0>(m, S.nbs[j], S.h[0], rank);
+                if (rank == 0) S.rbc[0] = S.bcs[j];
+                mine = mesh_classify<0>(S.h[0], S.ntri, rank, S.ccase[0], &counts);
+            } else if (has) {
+                mesh_stage_rows(m, S.nbs[j], S.h[worker], lane);
+                if (lane == 0) S.rbc[worker] = S.bcs[j];
+                mine = mesh_classify_rows(S.h[worker], S.ntri, lane, S.ccase[worker], &counts);
+            }
+            const int incl = wave_scan_incl(mine);
+            if (lane == 63) S.rcnt[wave] = incl;
+            __syncthreads();
+            int woff = 0, rtot = 0;
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) {
+                const int c = (int)S.rcnt[w];
+                woff += w < wave ? c : 0;
+                rtot += c;
+            }
+            mesh_round_out<kSched>(m, S, st, has, counts, woff + incl - mine, rtot, carry, out);
+            carry += rtot;
+            __syncthreads();  // the round's counts are rewritten by the next round
+        }
     }
 }
 

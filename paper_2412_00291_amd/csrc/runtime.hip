@@ -52,6 +52,17 @@ struct map_s {
     int dist_mode = kDistProjective;
     float cos_inc = 0.0f;      // point filter of the non-projective distance
     int64_t nimg_n = 0;        // pixels of the normal image (FrameView::nimg)
+    int64_t rcopy_n = 0;       // pixels of the range copy (FrameView::rcopy)
+    // The TSDF launch of the last LiDAR frame is enqueued by the map's next call: fused with
+    // label fusion when that call fuses camera labels, on its own otherwise.  It reads only
+    // the map's own buffers (the allocation launch copied the range image), so nothing of
+    // the caller's has to outlive the call that enqueued the frame.
+    struct {
+        bool active = false;
+        Pose T{};
+        uint32_t fid = 0;
+        hipStream_t s = nullptr;
+    } pend;
     int label_mode = kLabelCounts;
     // adjoint partial sums
     float *partial = nullptr;
@@ -149,8 +160,8 @@ static void free_all(map_t *m)
     m->prof_free.clear();
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hash,
                     m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
-                    m->f.tk_fslot, m->f.band, m->f.nimg, m->v.grad, m->v.logpost, m->lut_buf, m->partial,
-                    m->scan.wg_tris, m->scan.wg_blocks, m->scan.wg_off, m->rkeys};
+                    m->f.tk_fslot, m->f.band, m->f.nimg, m->f.rcopy, m->v.grad, m->v.logpost, m->lut_buf, m->partial,
+                    m->scan.wg_tris, m->scan.wg_blocks, m->scan.wg_off, m->scan.rec, m->scan.wg_nz, m->rkeys};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (m->h_ctr) (void)hipHostFree(m->h_ctr);
@@ -205,9 +216,15 @@ static hipError_t timed(map_t *m, int kid, hipStream_t s, F fn)
     return hipSuccess;
 }
 
+static int flush_pending(map_t *m);
+
 extern "C" int map_profile(map_t *m, uint32_t mask)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    {
+        const int rc = flush_pending(m);  // a pending launch is timed under the mask it was enqueued with
+        if (rc) return rc;
+    }
     m->prof_mask = mask & ((1u << MAP_KERNEL_COUNT) - 1);
     return MAP_OK;
 }
@@ -215,6 +232,10 @@ extern "C" int map_profile(map_t *m, uint32_t mask)
 extern "C" int map_profile_read(map_t *m, double *total_ms, int64_t *launches)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    {
+        const int rc = flush_pending(m);
+        if (rc) return rc;
+    }
     HIP_TRY(m, hipSetDevice(m->p.device));
     for (auto &p : m->prof_pending) {
         HIP_TRY(m, hipEventSynchronize(p.second.second));
@@ -309,6 +330,10 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&m->scan.wg_tris, kMaxMeshGrid * sizeof(long long)));
     CREATE_TRY(hipMalloc(&m->scan.wg_blocks, kMaxMeshGrid * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&m->scan.wg_off, kMaxMeshGrid * sizeof(long long)));
+    // records of the counting pass: a segment of ceil(max_blocks / G) + 256 per counting
+    // workgroup, for any grid G <= kMaxMeshGrid
+    CREATE_TRY(hipMalloc(&m->scan.rec, (nb + 257 * (size_t)kMaxMeshGrid) * sizeof(MeshRec)));
+    CREATE_TRY(hipMalloc(&m->scan.wg_nz, kMaxMeshGrid * sizeof(int32_t)));
     CREATE_TRY(hipHostMalloc((void **)&m->h_ctr, sizeof(Counters), hipHostMallocDefault));
     CREATE_TRY(hipHostMalloc((void **)&m->h_report, sizeof(MeshReport), hipHostMallocMapped | hipHostMallocCoherent));
     std::memset(m->h_report, 0, sizeof(MeshReport));
@@ -432,6 +457,14 @@ static int ensure_frame_scratch(map_t *m, const lidar_model *L, hipStream_t s)
         HIP_TRY(m, hipMalloc(&m->f.nimg, (size_t)L->rows * L->cols * sizeof(float4)));
         m->nimg_n = (int64_t)L->rows * L->cols;
     }
+    if ((int64_t)L->rows * L->cols > m->rcopy_n) {
+        HIP_TRY(m, hipStreamSynchronize(s));
+        if (m->f.rcopy) HIP_TRY(m, hipFree(m->f.rcopy));
+        m->f.rcopy = nullptr;
+        m->rcopy_n = 0;
+        HIP_TRY(m, hipMalloc(&m->f.rcopy, (size_t)L->rows * L->cols * sizeof(float)));
+        m->rcopy_n = (int64_t)L->rows * L->cols;
+    }
     if (m->f.tk_cap >= need) return MAP_OK;
     HIP_TRY(m, hipStreamSynchronize(s));
     FrameView &f = m->f;
@@ -439,8 +472,10 @@ static int ensure_frame_scratch(map_t *m, const lidar_model *L, hipStream_t s)
     for (void *p : old)
         if (p) HIP_TRY(m, hipFree(p));
     float4 *nimg = f.nimg;  // kept (sized separately)
+    float *rcopy = f.rcopy;
     f = FrameView{};
     f.nimg = nimg;
+    f.rcopy = rcopy;
     const uint64_t fcap = next_pow2((uint64_t)(2 * need));
     HIP_TRY(m, hipMalloc(&f.fkeys, fcap * sizeof(unsigned long long)));
     HIP_TRY(m, hipMalloc(&f.tk_key, need * sizeof(unsigned long long)));
@@ -461,6 +496,30 @@ static int grid_for(int64_t items, int per_block, int cap)
     return (int)(g < cap ? g : cap);
 }
 
+// Enqueue the last frame's TSDF launch (fused with the label fusion of the cameras in cs when
+// cs.n > 0), on the stream of the frame's allocation launch.
+static int launch_pending(map_t *m, const CameraSet &cs)
+{
+    if (!m->pend.active) return MAP_OK;
+    m->pend.active = false;
+    HIP_TRY(m, hipSetDevice(m->p.device));
+    const hipStream_t s = m->pend.s;
+    HIP_TRY(m, timed(m, cs.n > 0 ? MAP_K_TSDF_LABELS : MAP_K_TSDF, s, [&] {
+        return launch_tsdf(m->v, m->f, m->lut, m->pend.T, m->f.rcopy, m->pend.fid, m->sched[0],
+                           grid_for(m->f.tk_cap, 1, m->tsdf_grid), m->dist_mode, cs, m->label_mode, s);
+    }));
+    m->last_stream = s;
+    return MAP_OK;
+}
+
+static int flush_pending(map_t *m) { return launch_pending(m, CameraSet{}); }
+
+#define FLUSH_PENDING(m)                        \
+    do {                                        \
+        const int rc_ = flush_pending(m);       \
+        if (rc_) return rc_;                    \
+    } while (0)
+
 extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *range_dev, const float T_wl[16],
                                    void *stream)
 {
@@ -475,8 +534,10 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
         if (std::fabs((double)T_wl[4 * i + 3]) + (double)L->r_max + (double)m->p.truncation >= lim)
             return fail(m, MAP_ERR_INVALID_ARG, "integrate_lidar: scan reaches outside the map domain");
     hipStream_t s = (hipStream_t)stream;
+    int rc = flush_pending(m);
+    if (rc) return rc;
     HIP_TRY(m, hipSetDevice(m->p.device));
-    int rc = ensure_lut(m, L, s);
+    rc = ensure_lut(m, L, s);
     if (rc) return rc;
     rc = ensure_frame_scratch(m, L, s);
     if (rc) return rc;
@@ -484,11 +545,10 @@ extern "C" int map_integrate_lidar(map_t *m, const lidar_model *L, const float *
     HIP_TRY(m, timed(m, MAP_K_ALLOC, s, [&] {
         return launch_alloc(m->v, m->f, m->lut, T, range_dev, m->dist_mode, m->cos_inc, s);
     }));
-    const uint32_t fid = m->frame_id++;
-    HIP_TRY(m, timed(m, MAP_K_TSDF, s, [&] {
-        return launch_tsdf(m->v, m->f, m->lut, T, range_dev, fid, m->sched[0], grid_for(m->f.tk_cap, 1, m->tsdf_grid),
-                           m->dist_mode, s);
-    }));
+    m->pend.active = true;
+    m->pend.T = T;
+    m->pend.fid = m->frame_id++;
+    m->pend.s = s;
     m->last_stream = s;
     m->has_scan = true;
     return MAP_OK;
@@ -515,6 +575,12 @@ extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_mode
     if (!m->has_scan) return fail(m, MAP_ERR_NO_SCAN, "integrate_labels: no LiDAR frame integrated yet");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(m, hipSetDevice(m->p.device));
+    // a frame whose TSDF launch is still to come takes the first cameras into that launch
+    const bool fuse = m->pend.active && m->pend.s == s;
+    if (!fuse) {
+        const int rc = flush_pending(m);
+        if (rc) return rc;
+    }
     for (int i0 = 0; i0 < n; i0 += kMaxCams) {
         CameraSet cs{};
         cs.n = std::min(kMaxCams, n - i0);
@@ -523,6 +589,11 @@ extern "C" int map_integrate_labels_multi(map_t *m, int32_t n, const camera_mode
             cs.cam[j] = Camera{c.width, c.height, c.fx, c.fy, c.cx, c.cy};
             cs.T[j] = to_pose(T_wc + 16 * (i0 + j));
             cs.img[j] = labels_dev[i0 + j];
+        }
+        if (i0 == 0 && fuse) {
+            const int rc = launch_pending(m, cs);
+            if (rc) return rc;
+            continue;
         }
         HIP_TRY(m, timed(m, MAP_K_LABELS, s, [&] {
             return launch_labels(m->v, m->f, cs, m->sched[1], grid_for(m->f.tk_cap, 1, 2048), m->label_mode, s);
@@ -536,6 +607,7 @@ extern "C" int map_integrate_labels_lidar(map_t *m, const lidar_model *L, const 
                                           const float T_wl[16], void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (!L || !labels_dev || !T_wl || !L->elev_rad)
         return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: NULL argument");
     if (L->rows < 2 || L->cols < 8) return fail(m, MAP_ERR_INVALID_ARG, "integrate_labels_lidar: need rows >= 2, cols >= 8");
@@ -561,6 +633,7 @@ extern "C" int map_integrate_labels_lidar(map_t *m, const lidar_model *L, const 
 extern "C" int map_set_distance(map_t *m, int32_t mode, float max_incidence)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if ((mode != MAP_DIST_PROJECTIVE && mode != MAP_DIST_NONPROJECTIVE) || !std::isfinite(max_incidence) ||
         max_incidence < 0.0f)
         return fail(m, MAP_ERR_INVALID_ARG, "set_distance: mode 0 or 1 and a finite max_incidence >= 0");
@@ -579,6 +652,7 @@ extern "C" int map_set_distance(map_t *m, int32_t mode, float max_incidence)
 extern "C" int map_set_label_fusion(map_t *m, int32_t mode)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (mode != MAP_LABELS_COUNTS && mode != MAP_LABELS_LATEST && mode != MAP_LABELS_BAYES)
         return fail(m, MAP_ERR_INVALID_ARG, "set_label_fusion: mode 0, 1 or 2");
     HIP_TRY(m, hipSetDevice(m->p.device));
@@ -596,6 +670,7 @@ extern "C" int map_integrate_logprobs(map_t *m, const camera_model *cam, const f
                                       void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (!cam || !logp_dev || !T_wc) return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: NULL argument");
     if (!camera_ok(cam)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: bad camera model");
     if (!pose_ok(T_wc)) return fail(m, MAP_ERR_INVALID_ARG, "integrate_logprobs: pose is not a rigid transform");
@@ -625,6 +700,7 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
                                 int64_t cap_tris, int64_t *n_tris, void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (!n_tris || cap_tris < 0 || (mode != MAP_MESH_DIRTY && mode != MAP_MESH_ALL))
         return fail(m, MAP_ERR_INVALID_ARG, "extract_mesh: bad mode, capacity or n_tris");
     if (cap_tris > 0 && (!pos_dev || !lab_dev)) return fail(m, MAP_ERR_INVALID_ARG, "extract_mesh: NULL output");
@@ -632,6 +708,7 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     HIP_TRY(m, hipSetDevice(m->p.device));
     MeshOut out{pos_dev, lab_dev, (long long *)edge_keys_dev, (long long)cap_tris};
     const MeshGrid grid = mesh_grid(m->sched[2]);
+    m->scan.rec_cap = (int32_t)((m->p.max_blocks + grid.count - 1) / grid.count + 256);
     HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
         hipError_t e = launch_mesh_count(m->v, mode, m->scan, m->sched[2], grid, s);
         return e != hipSuccess ? e : launch_mesh_finish(m->v, mode, out, m->scan, m->d_report, m->sched[2], grid, s);
@@ -655,6 +732,7 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
 extern "C" int map_set_schedule(map_t *m, int32_t tsdf, int32_t labels, int32_t mesh)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     const int v[3] = {tsdf, labels, mesh};
     for (int i = 0; i < 3; ++i)
         if (v[i] != 0 && v[i] != 1) return fail(m, MAP_ERR_INVALID_ARG, "set_schedule: schedules are 0 or 1");
@@ -666,6 +744,7 @@ extern "C" int map_range_image(map_t *m, const lidar_model *L, const float *pts_
                                float *depth_dev, float *height_dev, void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (!L || !L->elev_rad || !depth_dev || n < 0 || n > INT32_MAX || (n > 0 && !pts_dev))
         return fail(m, MAP_ERR_INVALID_ARG, "range_image: bad arguments");
     if (!std::isfinite(F) || !std::isfinite(O)) return fail(m, MAP_ERR_INVALID_ARG, "range_image: F and O must be finite");
@@ -701,6 +780,7 @@ extern "C" int map_query_sdf(map_t *m, const float *pts_dev, int64_t n, float *s
                              uint8_t *valid_dev, void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (n < 0 || (n > 0 && (!pts_dev || !sdf_dev || !valid_dev)))
         return fail(m, MAP_ERR_INVALID_ARG, "query_sdf: bad arguments");
     hipStream_t s = (hipStream_t)stream;
@@ -714,6 +794,7 @@ extern "C" int map_sdf_pose_adjoint(map_t *m, const float *xi_dev, const float *
                                     float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (B < 1 || B > 65535 || N < 1 || !xi_dev || !pts_dev || !loss_dev || !gxi_dev)
         return fail(m, MAP_ERR_INVALID_ARG, "sdf_pose_adjoint: bad arguments");
     const int64_t nchunk = (N + 255) / 256;
@@ -842,6 +923,7 @@ extern "C" int map_sdf_pose_adjoint_noalloc(map_t *m, const float *xi_dev, const
                                             float *loss_dev, float *gxi_dev, float *gpts_dev, void *stream)
 {
     if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);
     if (B < 1 || B > 65535 || N < 1 || !xi_dev || !pts_dev || !loss_dev || !gxi_dev)
         return fail(m, MAP_ERR_INVALID_ARG, "sdf_pose_adjoint_noalloc: bad arguments");
     const int64_t nchunk = (N + 255) / 256;
@@ -863,6 +945,7 @@ extern "C" int map_sdf_pose_adjoint_noalloc(map_t *m, const float *xi_dev, const
 
 static int read_counters(map_t *m)
 {
+    FLUSH_PENDING(m);
     HIP_TRY(m, hipSetDevice(m->p.device));
     HIP_TRY(m, hipStreamSynchronize(m->last_stream));
     HIP_TRY(m, hipMemcpy(m->h_ctr, m->v.ctr, sizeof(Counters), hipMemcpyDeviceToHost));
@@ -1164,6 +1247,7 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
                         "map_batch_step: map %d is not in the plain modes (projective distance, vote counts)",
                         it.map_index);
     }
+    for (map_t *m : b->maps) FLUSH_PENDING(m);
     int tiles = 0;
     for (int i = 0; i < n; ++i) {
         const map_batch_item &it = items[i];

@@ -107,7 +107,7 @@ _sig = {
                                         ctypes.POINTER(_Quality), _P]),
 }
 
-KERNEL_NAMES = ["alloc", "tsdf", "labels", "mesh", "query", "adjoint", "batch", "range"]
+KERNEL_NAMES = ["alloc", "tsdf", "labels", "mesh", "query", "adjoint", "batch", "range", "tsdf_labels"]
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
     _fn.restype = _res
