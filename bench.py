@@ -481,83 +481,113 @@ def bench_label_modes(torch, frames=12, warm=2):
     return out
 
 
-def bench_batched(torch):
-    """Batched form: 16 street maps of uneven size (voxel 0.05-0.4 m, 16/32/64 beams,
-    1024-2048 columns, 4-8 frames each here, one 1280x720 camera), autotuned schedule,
-    against the same frames integrated by sequential plain calls."""
+_BATCHED = {}
+
+
+def _batched_frame(args):
+    """One frame of one batched map (worker process): (m, k, range, T_wl, label image, T_wc)."""
+    import synth
+    m, k = args
+    ws = _BATCHED.get("ws")
+    if ws is None:
+        ws = _BATCHED["ws"] = synth.batched_workloads(seed=3, n_maps=16)
+    f = ws[m].frame(k)
+    T, lab, _ = f.cams[0]
+    return m, k, f.range, f.T_wl, np.ascontiguousarray(lab), T
+
+
+def batched_max_blocks(voxel):
+    """Pool size of a batched map: room for its whole sequence at its voxel size."""
+    return {0.05: 1 << 19, 0.1: 1 << 18, 0.2: 1 << 17}.get(round(voxel, 2), 1 << 16)
+
+
+def bench_batched(torch, workers=None):
+    """Batched form at the batched workload's own frame counts: 16 street maps of uneven size
+    (voxel 0.05-0.4 m, 16/32/64 beams, 1024-2048 columns, 10-200 frames each, one 1280x720
+    camera), autotuned schedule, against the same frames integrated by sequential plain
+    calls.  A step integrates one frame into every map that still has frames; the frames
+    are generated in worker processes and resident in HBM before the timed runs."""
+    import multiprocessing as mp
     import synth
     from paper_2412_00291_amd import Batch, CameraModel, LidarModel, Map, MAP_MESH_DIRTY
     from paper_2412_00291_amd import autotune
     ws = synth.batched_workloads(seed=3, n_maps=16)
+    workers = workers or min(16, len(os.sched_getaffinity(0)))
+    jobs = [(m, k) for m, w in enumerate(ws) for k in range(w.n_frames)]
+    frames = [[None] * w.n_frames for w in ws]
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for i, (m, k, r, T, lab, Tc) in enumerate(pool.imap_unordered(_batched_frame, jobs, chunksize=8)):
+            frames[m][k] = (torch.from_numpy(r).cuda(), T, torch.from_numpy(lab).cuda(), Tc)
+            if (i + 1) % 500 == 0:
+                log(f"[bench] batched: {i + 1}/{len(jobs)} frames generated ({time.time() - t0:.0f} s)")
     data = []
     for m, w in enumerate(ws):
-        nfr = min(w.n_frames, 4 + m % 5)
         lid = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
         cam = CameraModel(*(getattr(w.cameras[0], k) for k in ("width", "height", "fx", "fy", "cx", "cy")))
-        frames = []
-        for k in range(nfr):
-            f = w.frame(k)
-            T, lab, _ = f.cams[0]
-            frames.append((torch.from_numpy(f.range).cuda(), f.T_wl,
-                           torch.from_numpy(np.ascontiguousarray(lab)).cuda(), T))
-        data.append((w, lid, cam, frames))
-    log(f"[bench] batched: {sum(len(d[3]) for d in data)} frames over {len(data)} maps generated")
+        data.append((w, lid, cam, frames[m]))
+    log(f"[bench] batched: {len(jobs)} frames over {len(data)} maps generated")
     torch.cuda.synchronize()
     cap = 1 << 21
     bufs = [(torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda"),
              torch.empty((cap, 3), dtype=torch.uint8, device="cuda")) for _ in data]
     n_steps = max(len(d[3]) for d in data)
-    mb = 1 << 16
     stream = torch.cuda.Stream()
 
     def items_for(k):
         out = []
-        for mi, (w, lid, cam, frames) in enumerate(data):
-            if k < len(frames):
-                r, T, lab, Tc = frames[k]
+        for mi, (w, lid, cam, fr) in enumerate(data):
+            if k < len(fr):
+                r, T, lab, Tc = fr[k]
                 out.append({"map_index": mi, "lidar": lid, "range": r, "T_wl": T, "cams": [cam],
                             "labels": [lab], "T_wc": [Tc], "pos": bufs[mi][0], "lab": bufs[mi][1]})
         return out
 
+    def new_maps():
+        return [Map(w.voxel, w.trunc, w.n_classes, batched_max_blocks(w.voxel)) for w, *_ in data]
+
     def build():
-        return Batch([Map(w.voxel, w.trunc, w.n_classes, mb) for w, *_ in data])
+        return Batch(new_maps())
 
     def run_step(batch, k):
         with torch.cuda.stream(stream):
             batch.step(items_for(k))
 
-    sig = "street16-seed3-" + "-".join(str(len(d[3])) for d in data)
+    sig = "street16-seed3-real-" + "-".join(str(len(d[3])) for d in data)
     sched, grid, timings = autotune.tune(sig, build, run_step, n_steps=2)
     log(f"[bench] batched: autotuner chose schedule {sched}, grid {grid}")
 
     # batched, all steps (items prepared beforehand, as a caller holding its frames would);
-    # HIP events on the step stream give the device time of each step beside the wall time
+    # HIP events on the step stream give the device time beside the wall time
     step_items = [items_for(k) for k in range(n_steps)]
     batch = build()
     batch.configure(sched, grid, True)
     with torch.cuda.stream(stream):
         batch.step(step_items[0])  # first step: scratch sizing and graph capture (untimed)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
+        e0.record(stream)
         for k in range(1, n_steps):
-            ev[k][0].record(stream)
             batch.step(step_items[k])
-            ev[k][1].record(stream)
+        e1.record(stream)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    gpu_batch = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(1, n_steps))
+    gpu_batch = e0.elapsed_time(e1)
     U = 0
     for m in batch.maps:
-        U += m.stats()[1]["updates"]
-    # sequential plain calls over the same frames
-    maps = [Map(w.voxel, w.trunc, w.n_classes, mb) for w, *_ in data]
+        U += m.stats()[1]["allocated"]
+    for m in batch.maps:
+        m.close()
+    batch.close()
+    # sequential plain calls over the same frames, on fresh maps
+    maps = new_maps()
 
     def seq_step(k):
-        for mi, (w, lid, cam, frames) in enumerate(data):
-            if k < len(frames):
-                r, T, lab, Tc = frames[k]
+        for mi, (w, lid, cam, fr) in enumerate(data):
+            if k < len(fr):
+                r, T, lab, Tc = fr[k]
                 m = maps[mi]
                 m.integrate_lidar(lid, r, T)
                 m.integrate_labels_multi([cam], [lab], [Tc])
@@ -567,18 +597,19 @@ def bench_batched(torch):
     torch.cuda.synchronize()
     cur = torch.cuda.current_stream()
     t0 = time.perf_counter()
+    e0.record(cur)
     for k in range(1, n_steps):
-        ev[k][0].record(cur)
         seq_step(k)
-        ev[k][1].record(cur)
+    e1.record(cur)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    gpu_seq = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(1, n_steps))
+    gpu_seq = e0.elapsed_time(e1)
+    blocks_seq = sum(m.stats()[1]["allocated"] for m in maps)
     frames_timed = sum(max(len(d[3]) - 1, 0) for d in data)
-    for m in maps + batch.maps:
+    for m in maps:
         m.close()
-    batch.close()
-    return {"workload": "16 street maps, voxel 0.05-0.4 m, 16/32/64 x 1024-2048, 4-8 frames, 1 camera",
+    return {"workload": "16 street maps, voxel 0.05-0.4 m, 16/32/64 x 1024-2048, "
+                        f"{min(len(d[3]) for d in data)}-{max(len(d[3]) for d in data)} frames each, 1 camera",
             "steps_timed": n_steps - 1, "map_frames_timed": frames_timed,
             "schedule": {"tsdf": ["workgroup-per-block", "wavefront-per-block"][sched & 1],
                          "labels": ["workgroup-per-block", "wavefront-per-block"][sched >> 1],
@@ -589,7 +620,9 @@ def bench_batched(torch):
             "speedup_vs_sequential": t_seq / t_batch,
             "stream_ms_per_step_batched": gpu_batch / (n_steps - 1),
             "stream_ms_per_step_sequential": gpu_seq / (n_steps - 1),
-            "last_frame_updates_sum": U}
+            "ms_per_map_frame_batched": 1e3 * t_batch / frames_timed,
+            "ms_per_map_frame_sequential": 1e3 * t_seq / frames_timed,
+            "allocated_blocks_end": {"batched": U, "sequential": blocks_seq}}
 
 
 _CAMPUS = {}
@@ -606,7 +639,7 @@ def _campus_frame(args):
     return k, f.range, [np.ascontiguousarray(l) for _, l, _ in f.cams], [T for T, _, _ in f.cams]
 
 
-def bench_campus(torch, warm=300, timed=200, workers=None):
+def bench_campus(torch, warm=1800, timed=200, workers=None):
     """Large-scale form: 128x2048 scans and two 1920x1080 cameras on the campus loop, in a
     map with room for 2M blocks (~50 GB).  Frames 0..warm-1 grow the map (scan and dirty
     meshing; no labels), then frames warm..warm+timed-1 (scan, both label images, dirty

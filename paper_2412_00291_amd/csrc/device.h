@@ -487,19 +487,40 @@ __device__ __forceinline__ T coherent_load(T *p)
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Frame state after allocation, read by a later launch (plain loads: the counters'
-// last atomic updates were performed before that launch began).
-__device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameView &f)
+// last atomic updates were performed before that launch began).  Split in two so a
+// launch can issue the loads before other start-up work and use them after it.
+struct FrameRaw {
+    unsigned long long tn;
+    int32_t used, overflow;
+    uint32_t epoch;
+};
+
+__device__ __forceinline__ FrameRaw frame_raw(const MapView &m)
 {
     const Counters *c = m.ctr;
-    const unsigned long long tn = c->touched_new;
+    FrameRaw r;
+    r.tn = c->touched_new;
+    r.used = c->pool_used;
+    r.epoch = c->dirty_epoch;
+    r.overflow = c->overflow;
+    return r;
+}
+
+__device__ __forceinline__ FrameState frame_state_of(const FrameRaw &r, const MapView &m, const FrameView &f)
+{
     FrameState s;
-    const int n_touched = (int)(tn & 0xFFFFFFFFull);
-    s.n_new = (int)(tn >> 32);
-    s.used = c->pool_used;
-    s.epoch = c->dirty_epoch;
-    s.ok = c->overflow == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
+    const int n_touched = (int)(r.tn & 0xFFFFFFFFull);
+    s.n_new = (int)(r.tn >> 32);
+    s.used = r.used;
+    s.epoch = r.epoch;
+    s.ok = r.overflow == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
     s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
     return s;
+}
+
+__device__ __forceinline__ FrameState frame_state(const MapView &m, const FrameView &f)
+{
+    return frame_state_of(frame_raw(m), m, f);
 }
 
 // The same, read in the launch whose atomics wrote the counters (device-coherent loads).
@@ -545,6 +566,28 @@ __device__ __forceinline__ bool ticket_arrive(Ticket &t)
     wait_memory();  // this workgroup's earlier memory operations complete first
     if (atomicAdd(&t.leaf[l * kLeafPad], 1ull) + 1ull != expect) return false;
     if (atomicAdd(&t.root[0], 1ull) + 1ull != leaves) return false;
+    for (unsigned i = 0; i < leaves; ++i) atomicExch(&t.leaf[i * kLeafPad], 0ull);
+    atomicExch(&t.root[0], 0ull);
+    return true;
+}
+
+// The same ticket carrying a sum: each workgroup arrives with its count (below 2^40 in
+// total), and the last one receives the launch's total in *total, so no counter has to be
+// read back after the ticket.  Nothing the workgroups wrote is read in the launch, so a
+// workgroup arrives without waiting for its stores.
+__device__ __forceinline__ bool ticket_arrive_sum(Ticket &t, unsigned long long mine, unsigned long long *total)
+{
+    constexpr unsigned long long kOne = 1ull << 40, kMask = kOne - 1;
+    const unsigned G = gridDim.x;
+    const unsigned leaves = G < (unsigned)kLeaves ? G : (unsigned)kLeaves;
+    const unsigned l = blockIdx.x % leaves;
+    const unsigned long long expect = (G - l + leaves - 1) / leaves;  // workgroups of leaf l
+    const unsigned long long o = atomicAdd(&t.leaf[l * kLeafPad], kOne | mine);
+    if ((o >> 40) + 1ull != expect) return false;
+    const unsigned long long leaf_sum = (o & kMask) + mine;
+    const unsigned long long r = atomicAdd(&t.root[0], kOne | leaf_sum);
+    if ((r >> 40) + 1ull != leaves) return false;
+    *total = (r & kMask) + leaf_sum;
     for (unsigned i = 0; i < leaves; ++i) atomicExch(&t.leaf[i * kLeafPad], 0ull);
     atomicExch(&t.root[0], 0ull);
     return true;

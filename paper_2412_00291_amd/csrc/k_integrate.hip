@@ -129,12 +129,12 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
     constexpr int kChunk = kWidth / 8;  // entries per chunk: eight marking lanes each
     extern __shared__ float2 s_lut[];
     __shared__ int s_slot[kThreads / 8];
-    __shared__ int s_last;
     __shared__ unsigned long long s_sum[kThreads / 64];
     __shared__ unsigned long long s_vsum[kThreads / 64];
     __shared__ ChunkBand<kLab ? kChunk : 1> s_cb[kLab ? (kSched == 0 ? 1 : kThreads / 64) : 1];
+    const FrameRaw raw = frame_raw(m);  // in flight with the table copy
     if (kLdsLut) stage_lut(L, s_lut);
-    const FrameState fs = frame_state(m, f);
+    const FrameState fs = frame_state_of(raw, m, f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int first = kSched == 0 ? (int)blockIdx.x : (int)blockIdx.x * (kThreads / 64) + wave;
@@ -213,18 +213,16 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
         s_vsum[wave] = wv;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {  // the last workgroup closes the frame with the launch's update count
         unsigned long long t = 0, tv = 0;
         for (int i = 0; i < kThreads / 64; ++i) {
             t += s_sum[i];
             tv += s_vsum[i];
         }
-        if (t) spread_add(m.sync->updates, t);
         if (kLab && tv) spread_add(m.sync->votes, tv);
-        s_last = ticket_arrive(m.sync->tsdf);
+        unsigned long long total = 0;
+        if (ticket_arrive_sum(m.sync->tsdf, t, &total)) close_frame(m, fs, total);
     }
-    __syncthreads();
-    if (s_last && wave == 0) close_frame_wave(m, fs, false);
 }
 
 template <bool kNP, int kLab>

@@ -31,8 +31,11 @@ __global__ __launch_bounds__(kThreads) void k_mesh_emit(MapView m, int mode, Mes
     __shared__ MeshStage st;
     __shared__ long long s_red[3 * (kThreads / 64)];
     const TableRegs tab = mesh_tables_load<true>();  // in flight with the counts
+    const int k = g_count / (int)gridDim.x;
+    // the record counts of this workgroup's counting workgroups, also in flight with the counts
+    const int my_nz = threadIdx.x < k ? scan.wg_nz[blockIdx.x + threadIdx.x * gridDim.x] : 0;
     const long long base = mesh_emit_base(m, mode, scan.wg_tris, scan.wg_blocks, g_count, out.cap, report, s_red);
-    mesh_emit_recs<kSched>(m, scan, g_count / (int)gridDim.x, base, out, S, st, tab);
+    mesh_emit_recs<kSched>(m, scan, k, my_nz, base, out, S, st, tab);
 }
 
 MeshGrid mesh_grid(int schedule)

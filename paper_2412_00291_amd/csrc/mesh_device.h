@@ -578,22 +578,19 @@ __device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_
 // read at once into the lookup arrays), triangles from output index `base` on.  Rounds as
 // in mesh_emit_wg.
 template <int kSched>
-__device__ __forceinline__ void mesh_emit_recs(const MapView &m, const MeshScan &scan, int k, long long base,
-                                               const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st,
-                                               const TableRegs &tab)
+__device__ __forceinline__ void mesh_emit_recs(const MapView &m, const MeshScan &scan, int k, int my_nz,
+                                               long long base, const MeshOut &out, MeshSmem<kSched, HaloFull> &S,
+                                               MeshStage &st, const TableRegs &tab)
 {
     constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rank = kSched == 0 ? (int)threadIdx.x : lane;
     const int worker = kSched == 0 ? 0 : wave;
     const int G = (int)gridDim.x;
-    if (threadIdx.x == 0) {  // the record counts of this workgroup's counting workgroups
-        int p = 0;
-        S.rpre[0] = 0;
-        for (int j = 0; j < k; ++j) {
-            p += scan.wg_nz[blockIdx.x + j * G];
-            S.rpre[j + 1] = p;
-        }
+    if (wave == 0) {  // prefix of the record counts (thread j < k holds counting workgroup w + j G's)
+        const int incl = wave_scan_incl(my_nz);
+        if (lane < k) S.rpre[lane + 1] = incl;
+        if (lane == 0) S.rpre[0] = 0;
     }
     mesh_tables_store<true>(S, tab);
     __syncthreads();
