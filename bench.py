@@ -368,7 +368,7 @@ def bench_nonprojective(torch, frames=24, warm=4):
     m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
     m.set_distance(MAP_DIST_NONPROJECTIVE, float(np.deg2rad(80.0)))
     times, stats = [], []
-    mask = (1 << KERNEL_NAMES.index("alloc")) | (1 << KERNEL_NAMES.index("tsdf"))
+    mask = sum(1 << KERNEL_NAMES.index(k) for k in ("alloc", "tsdf", "tsdf_labels"))
     for k, (r, labs, T, Tcs) in enumerate(dev):
         if k == warm:
             torch.cuda.synchronize()
@@ -400,17 +400,23 @@ def bench_nonprojective(torch, frames=24, warm=4):
     n = len(stats)
     U = sum(s["updates"] for s in stats)
     Tk = sum(s["touched"] for s in stats)
+    V = sum(s["votes"] for s in stats)
     # alloc: range + its two neighbours' rows through the caches (4 B), normal image write
     # (16 B), probe + list per touched block; TSDF: (D, W) and the gradient read and
-    # written per update, the normal image read, the touched list
+    # written per update, the normal image read, the touched list; with the frame's camera
+    # labels fused into the TSDF launch, the label bytes of the projective model as well
     alloc_b = n * (4 * R * C + 16 * R * C) + 16 * Tk
     tsdf_b = 16 * U + 24 * U + n * 16 * R * C + 16 * Tk
+    fused = prof["tsdf_labels"][1] > 0
+    if fused:
+        tsdf_b += 8 * V + n * sum(c.width * c.height for c in cams)
     out = {"workload": "street-64x2048-v0.1, non-projective distance (Eq. 4), 80 deg point filter, 4 cameras",
            "frames_timed": n, "ms_per_frame_p50": float(np.median(times) * 1e3),
            "ms_per_frame_p90": float(np.percentile(times, 90) * 1e3),
-           "voxel_updates_per_s": U / sum(times), "updates_per_frame": U / n}
-    for name, b in (("alloc", alloc_b), ("tsdf", tsdf_b)):
-        ms, launches = prof[name]
+           "voxel_updates_per_s": U / sum(times), "updates_per_frame": U / n,
+           "tsdf_launch": "TSDF with the camera labels fused in" if fused else "TSDF"}
+    for name, key, b in (("alloc", "alloc", alloc_b), ("tsdf", "tsdf_labels" if fused else "tsdf", tsdf_b)):
+        ms, launches = prof[key]
         out[f"{name}_avg_us"] = 1e3 * ms / max(launches, 1)
         out[f"{name}_roofline"] = {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                                    "unit": "GB/s", "frac": b / (ms * 1e-3) / PEAK_HBM}
@@ -431,24 +437,34 @@ def bench_label_modes(torch, frames=12, warm=2):
     L = w.n_classes
     out = {}
     mask = 1 << KERNEL_NAMES.index("labels")
-    # latest label wins
+    # latest label wins: the four label images are fused into the frame's TSDF launch, so
+    # that launch is timed and priced at the TSDF bytes plus the label bytes
+    fmask = (1 << KERNEL_NAMES.index("tsdf_labels")) | mask
     m = Map(w.voxel, w.trunc, L, w.max_blocks)
     m.set_label_fusion(MAP_LABELS_LATEST)
     dev = [(torch.from_numpy(f.range).cuda(), [torch.from_numpy(np.ascontiguousarray(l)).cuda() for _, l, _ in f.cams],
             f.T_wl, [T for T, _, _ in f.cams]) for f in hf]
-    votes = 0
+    votes = upd = touched = 0
     for k, (r, labs, T, Tcs) in enumerate(dev):
         if k == warm:
             torch.cuda.synchronize()
-            m.profile(mask)
+            m.profile(fmask)
         m.integrate_lidar(lid, r, T)
         m.integrate_labels_multi(cams, labs, Tcs)
         if k >= warm:
-            votes += m.stats()[1]["votes"]
-    ms, launches = m.profile_read()["labels"]
+            st = m.stats()[1]
+            votes += st["votes"]
+            upd += st["updates"]
+            touched += st["touched"]
+    prof = m.profile_read()
     m.close()
+    fused = prof["tsdf_labels"][1] > 0
+    ms, launches = prof["tsdf_labels"] if fused else prof["labels"]
     b = 2 * votes + launches * sum(c.width * c.height for c in cams)  # fused read + write per vote, images
+    if fused:
+        b += 16 * upd + launches * 4 * w.lidar.rows * w.lidar.cols + 16 * touched
     out["latest"] = {"workload": "street-64x2048-v0.1, 4 x 1280x720 label images, latest label wins",
+                     "kernel": "TSDF with the labels fused in" if fused else "labels",
                      "launches": launches, "kernel_us": 1e3 * ms / max(launches, 1),
                      "votes_per_s": votes / (ms * 1e-3),
                      "roofline": {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
@@ -639,16 +655,18 @@ def _campus_frame(args):
     return k, f.range, [np.ascontiguousarray(l) for _, l, _ in f.cams], [T for T, _, _ in f.cams]
 
 
-def bench_campus(torch, warm=1800, timed=200, workers=None):
+def bench_campus(torch, warm=1500, timed=100, window=100, workers=None):
     """Large-scale form: 128x2048 scans and two 1920x1080 cameras on the campus loop, in a
     map with room for 2M blocks (~50 GB).  Frames 0..warm-1 grow the map (scan and dirty
-    meshing; no labels), then frames warm..warm+timed-1 (scan, both label images, dirty
-    meshing) are timed one by one: the steady state once the map has grown, with early and
-    late frames of the window compared (meshing sees only the dirty blocks).  The frames are
-    generated in worker processes before the GPU work and uploaded to HBM first."""
+    meshing; no labels); meshing alone is timed with events over two windows of the growth,
+    early (frames 300-399) and late (the last `window` growth frames), to compare its cost
+    per meshed block at two map sizes.  Then frames warm..warm+timed-1 (scan, both label
+    images, dirty meshing) are timed one by one, wall clock: the steady state once the map
+    has grown.  The frames are generated in worker processes before the GPU work and
+    uploaded to HBM first."""
     import multiprocessing as mp
     import synth
-    from paper_2412_00291_amd import CameraModel, LidarModel, Map, MAP_MESH_DIRTY
+    from paper_2412_00291_amd import CameraModel, KERNEL_NAMES, LidarModel, Map, MAP_MESH_DIRTY
     n = warm + timed
     w = synth.campus_workload(n_frames=n)
     lid = LidarModel(w.lidar.rows, w.lidar.cols, w.lidar.elev_rad, w.lidar.r_max)
@@ -667,10 +685,19 @@ def bench_campus(torch, warm=1800, timed=200, workers=None):
     pos = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
     lab = torch.empty((cap, 3), dtype=torch.uint8, device="cuda")
     m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+    mesh_mask = 1 << KERNEL_NAMES.index("mesh")
+    windows = {"early": (300, 300 + window), "late": (warm - window, warm)}
+    win = {}
     times, U, alloc, mesh_blocks = [], 0, [], []
     for k in range(n):
         r, labs, Tcs = frames[k]
         T = w.poses[k]
+        for name, (a, b) in windows.items():
+            if k == a:
+                torch.cuda.synchronize()
+                m.profile(mesh_mask)
+                win[name] = {"frames": f"{a}-{b - 1}", "allocated_blocks_start": m.stats()[1]["allocated"],
+                             "mesh_blocks": 0}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         m.integrate_lidar(lid, r, T)
@@ -678,6 +705,18 @@ def bench_campus(torch, warm=1800, timed=200, workers=None):
             m.integrate_labels_multi(cams, labs, Tcs)
         m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
         t1 = time.perf_counter()
+        for name, (a, b) in windows.items():
+            if a <= k < b:
+                win[name]["mesh_blocks"] += m.stats()[1]["mesh_blocks"]
+            if k == b - 1:
+                torch.cuda.synchronize()
+                ms, launches = m.profile_read()["mesh"]
+                m.profile(0)
+                d = win[name]
+                d["allocated_blocks_end"] = m.stats()[1]["allocated"]
+                d["mesh_us_per_frame"] = 1e3 * ms / launches
+                d["mesh_blocks_per_frame"] = d["mesh_blocks"] / launches
+                d["mesh_ns_per_block"] = 1e6 * ms / max(d.pop("mesh_blocks"), 1)
         if k >= warm:
             times.append(t1 - t0)
             st, s = m.stats()
@@ -687,15 +726,55 @@ def bench_campus(torch, warm=1800, timed=200, workers=None):
         if (k + 1) % 100 == 0:
             log(f"[bench] campus: frame {k + 1}/{n}")
     m.close()
+    del pos, lab
+    fine = bench_campus_fine(torch, w, lid, frames, warm, window)
     t = np.array(times) * 1e3
-    q = max(len(t) // 5, 1)
     return {"workload": f"{w.name}, 2 x 1920x1080 cameras, L=20, max_blocks {w.max_blocks}",
             "frames": f"{warm} frames of growth (scan and meshing), then frames {warm}-{n - 1} timed",
             "frames_timed": len(times), "ms_per_frame_p50": float(np.median(t)),
             "ms_per_frame_p90": float(np.percentile(t, 90)), "voxel_updates_per_s": U / (t.sum() * 1e-3),
-            "ms_per_frame_first_fifth": float(np.mean(t[:q])), "ms_per_frame_last_fifth": float(np.mean(t[-q:])),
             "mesh_blocks_per_frame": float(np.mean(mesh_blocks)),
-            "allocated_blocks_start": int(alloc[0]), "allocated_blocks_end": int(alloc[-1])}
+            "allocated_blocks_start": int(alloc[0]), "allocated_blocks_end": int(alloc[-1]),
+            "mesh_windows": win, "fine_voxels": fine}
+
+
+def bench_campus_fine(torch, w, lid, frames, warm, window):
+    """Dirty meshing of a map of millions of blocks: the campus growth frames (scan and
+    dirty meshing) at 0.05 m voxels (tau 0.15 m, one class) into a map of up to 4M blocks,
+    once with the dirty blocks found in the dirty bitmap (the default above 2^19 blocks) and
+    once by the sweep of the slots (threshold never reached); meshing timed with events
+    over the last `window` frames of each run."""
+    from paper_2412_00291_amd import KERNEL_NAMES, Map, MAP_MESH_DIRTY
+    cap = 16_000_000
+    pos = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
+    lab = torch.empty((cap, 3), dtype=torch.uint8, device="cuda")
+    mesh_mask = 1 << KERNEL_NAMES.index("mesh")
+    out = {"workload": f"campus frames 0-{warm - 1}, 0.05 m voxels, tau 0.15 m, max_blocks 4000000",
+           "frames_timed": f"{warm - window}-{warm - 1}"}
+    for name, threshold in (("bitmap", -1), ("sweep", 1 << 40)):
+        m = Map(0.05, 0.15, 1, 4_000_000)
+        m.set_dirty_bitmap(threshold)
+        from_bits = blocks = over = 0
+        for k in range(warm):
+            if k == warm - window:
+                torch.cuda.synchronize()
+                m.profile(mesh_mask)
+                a0 = m.stats()[1]["allocated"]
+            m.integrate_lidar(lid, frames[k][0], w.poses[k])
+            st, n = m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None, allow_small=True)
+            over += n > cap
+            if k >= warm - window:
+                s = m.stats()[1]
+                from_bits += s["mesh_from_bitmap"]
+                blocks += s["mesh_blocks"]
+        torch.cuda.synchronize()
+        ms, launches = m.profile_read()["mesh"]
+        out[name] = {"allocated_blocks_start": a0, "allocated_blocks_end": m.stats()[1]["allocated"],
+                     "mesh_us_per_frame": 1e3 * ms / launches, "mesh_blocks_per_frame": blocks / launches,
+                     "extractions_from_bitmap": from_bits, "extractions_over_capacity": over}
+        m.close()
+        log(f"[bench] campus at 0.05 m, {name}: {out[name]}")
+    return out
 
 
 def calibrate_copy(torch):

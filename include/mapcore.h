@@ -76,6 +76,8 @@ typedef struct {
     int64_t triangles;   /* triangles of the last extraction */
     int64_t allocated;   /* blocks in the map */
     int64_t frames;      /* accepted LiDAR frames */
+    int64_t mesh_from_bitmap; /* 1 if the last extraction found its dirty blocks in the
+                                 dirty bitmap, 0 if by a sweep of the slots */
 } map_frame_stats;
 
 /* Create an empty map on params->device: allocates and pre-initialises the block pool
@@ -141,6 +143,17 @@ int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
  * workgroup per block, 1 = one wavefront per block.  Results are identical either way;
  * only the speed differs.  Default 0, 0, 0. */
 int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
+
+/* Candidates of DIRTY meshing (Sec. IV-C.3: only the blocks changed since the last
+ * extraction are re-meshed).  The counting pass finds the dirty blocks either by a sweep of the
+ * allocated slots (one coordinate read per slot) or, once the map holds more than
+ * min_blocks blocks, from a dirty bitmap of one bit per slot that the TSDF pass keeps (one
+ * bitmap read per slot, kept in the cache, and one coordinate read per dirty block).  An
+ * extraction that follows a frame which ended at or below the threshold sweeps once more.
+ * min_blocks < 0 (the default) takes the pool size one sweep round covers: 256 slots per
+ * workgroup of the counting grid, 2^19 for a 2048-workgroup grid.  Results are identical
+ * either way; only the speed differs. */
+int map_set_dirty_bitmap(map_t *map, int64_t min_blocks);
 
 /* Label fusion from a label range image: the scan's points labelled by a point-cloud
  * segmentation network, the semantic measurements of the paper's LiDAR experiments

@@ -10,7 +10,6 @@
 
 namespace mc {
 
-constexpr int kThreads = 256;
 constexpr int kLdsKeys = 2048;                    // per-workgroup de-duplication table (16 KiB)
 constexpr int kKeysPerThread = kLdsKeys / kThreads;
 constexpr int kHalo = 9;
@@ -515,6 +514,7 @@ __device__ __forceinline__ FrameState frame_state_of(const FrameRaw &r, const Ma
     s.epoch = r.epoch;
     s.ok = r.overflow == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
     s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
+    s.bits = s.used + s.n_new > m.bits_from;
     return s;
 }
 
@@ -535,6 +535,7 @@ __device__ __forceinline__ FrameState frame_state_coherent(const MapView &m, con
     s.epoch = coherent_load(&c->dirty_epoch);
     s.ok = coherent_load(&c->overflow) == 0 && n_touched <= f.tk_cap && s.used + s.n_new <= m.max_blocks;
     s.n_list = n_touched < f.tk_cap ? n_touched : f.tk_cap;
+    s.bits = s.used + s.n_new > m.bits_from;
     return s;
 }
 
@@ -623,6 +624,14 @@ __device__ __forceinline__ int hash_find_old(const MapView &m, unsigned long lon
     return -1;
 }
 
+// Set a slot's bit in the dirty bitmap (layout: MapView::dbits).
+__device__ __forceinline__ void mark_bit(const MapView &m, int slot)
+{
+    const uint32_t s = (uint32_t)slot, G = (uint32_t)m.bits_grid;
+    const uint32_t j = s / G, w = s - j * G;
+    atomicOr(&m.dbits[(size_t)w * (uint32_t)m.bits_wpw + (j >> 5)], 1u << (j & 31));
+}
+
 // Commit of touched entry e by one thread: clear its frame-set slot, and give a new block
 // its pool slot (after the used ones, in rank order) and insert it.  Returns the slot.
 __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f, const FrameState &fs, int e,
@@ -634,16 +643,19 @@ __device__ __forceinline__ int commit_entry(const MapView &m, const FrameView &f
         slot = fs.used + f.tk_rank[e];
         const int3 bc = unpack_key(key);
         m.coords[slot] = make_int4(bc.x, bc.y, bc.z, (int)fs.epoch);  // a new block is dirty
+        if (fs.bits) mark_bit(m, slot);
         hash_insert_new(m, key, slot, frame_id);
         f.tk_slot[e] = slot;
     }
     return slot;
 }
 
-// Mark a block dirty: its coordinates' fourth component holds the epoch.
-__device__ __forceinline__ void mark_dirty(const MapView &m, int slot, uint32_t epoch)
+// Mark a block dirty: its coordinates' fourth component holds the epoch; with bits, its
+// bit in the dirty bitmap is set as well (several marks of one block set it again).
+__device__ __forceinline__ void mark_dirty(const MapView &m, int slot, uint32_t epoch, bool bits)
 {
     reinterpret_cast<int *>(&m.coords[slot])[3] = (int)epoch;
+    if (bits) mark_bit(m, slot);
 }
 
 // Whether a block is dirty in epoch (one 4-byte read).
@@ -831,6 +843,7 @@ __device__ __forceinline__ void close_frame(const MapView &m, const FrameState &
         c->last_touched = fs.n_list;
         c->last_new = fs.n_new;
         c->last_updates = updates;
+        if (!fs.bits) c->bits_gap = 1;  // this frame's marks are not in the dirty bitmap
     } else {
         c->frame_ok = 0;
         c->status = -2;  // MAP_ERR_CAPACITY, reported by the next synchronising call

@@ -28,6 +28,9 @@ struct Counters {
     int32_t last_new;
     int32_t overflow;      // touched list overflow (cannot happen with the sizing rule)
     uint32_t extractions;  // extractions whose totals have been reported
+    int32_t bits_gap;      // nonzero when a frame since the dirty set was last cleared did not
+                           // mark the dirty bitmap (the next DIRTY extraction sweeps the slots)
+    int32_t mesh_bits;     // the last extraction's candidates came from the dirty bitmap
 };
 
 // Same-address device atomics are serialised (about 12 ns apart on gfx950), so a value
@@ -90,14 +93,24 @@ struct MapView {
                               // distance (x, y, z planes); null until that distance is enabled
     float *logpost;           // [max_blocks][L][512] class log-posteriors of Bayesian label fusion
                               // (largest 0); null until that fusion is enabled
+    uint32_t *dbits;          // dirty bitmap in the meshing counting pass's order: slot
+                              // s = w + j bits_grid is bit j % 32 of word w bits_wpw + j / 32,
+                              // so counting workgroup w owns words [w bits_wpw, (w + 1) bits_wpw);
+                              // a superset of the dirty set whenever ctr->bits_gap is 0 (kept
+                              // only by frames that end with more than bits_from blocks)
     Counters *ctr;
     SyncState *sync;
+    int32_t bits_from;        // frames mark, and DIRTY extractions read, the bitmap above this
+                              // many allocated blocks (below it the slot sweep is one pass)
+    int32_t bits_grid;        // counting grid the bitmap is laid out for
+    int32_t bits_wpw;         // words per counting workgroup: ceil(ceil(max_blocks / grid) / 32)
     uint32_t hmask;
     int32_t n_classes;
     int32_t max_blocks;
     float nu, tau;
 };
 
+constexpr int kThreads = 256;      // threads of every workgroup of the library's kernels
 constexpr int kMaxMeshGrid = 4096;  // workgroups of a meshing pass (and of a batched phase)
 
 // A block with triangles, recorded by the counting pass of a per-map extraction for the
@@ -248,6 +261,7 @@ struct FrameState {
     int32_t n_list, n_new, used;
     uint32_t epoch;
     int32_t ok;
+    int32_t bits;  // the frame marks the dirty bitmap (the pool ends above bits_from)
 };
 
 struct BatchCtl {  // device
@@ -295,7 +309,7 @@ MeshGrid batch_mesh_grid();
 // Meshing is the counting pass, then the scan and the emitting pass (which may run on
 // another stream once the counting pass is done).
 hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, int schedule, MeshGrid grid,
-                             hipStream_t s);
+                             bool allow_bits, hipStream_t s);
 hipError_t launch_mesh_finish(const MapView &m, int mode, const MeshOut &out, const MeshScan &scan,
                               MeshReport *report, int schedule, MeshGrid grid, hipStream_t s);
 hipError_t launch_labels_lidar(const MapView &m, const FrameView &f, const LidarLUT &lut, const Pose &T,

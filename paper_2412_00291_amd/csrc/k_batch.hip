@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_tsdf(BatchMap *maps, BatchCt
                 if (fs.ok) {
                     const MapView &v = maps[mi].v;
                     const int s = neighbour_slot(v, rank & 7, unpack_key(maps[mi].f.tk_key[e]), si, maps[mi].frame_id);
-                    if (s >= 0) mark_dirty(v, s, fs.epoch);
+                    if (s >= 0) mark_dirty(v, s, fs.epoch, fs.bits);
                 }
             }
         }

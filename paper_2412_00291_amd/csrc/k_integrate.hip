@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_tsdf(MapView m, FrameView f, Lidar
             const int si = kSched == 0 ? s_slot[i] : __shfl(my_slot, i, 64);
             if (em < fs.n_list) {
                 const int s = neighbour_slot(m, rank & 7, unpack_key(f.tk_key[em]), si, frame_id);
-                if (s >= 0) mark_dirty(m, s, fs.epoch);
+                if (s >= 0) mark_dirty(m, s, fs.epoch, fs.bits);
             }
         }
         if (kSched == 0) __syncthreads();  // s_slot is rewritten by the next chunk

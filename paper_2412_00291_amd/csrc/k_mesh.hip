@@ -7,19 +7,29 @@
 
 namespace mc {
 
-__global__ __launch_bounds__(kThreads) void k_mesh_count(MapView m, int mode, MeshScan scan)
+// A DIRTY extraction takes its candidates from the dirty bitmap (and clears it) when the
+// map holds more than bits_from blocks, every frame since the bitmap was last cleared has
+// marked it, the bitmap is laid out for this grid and the host allows it (allow_bits: no
+// change of layout since the last DIRTY extraction); otherwise it sweeps the slots.
+__global__ __launch_bounds__(kThreads, 8) void k_mesh_count(MapView m, int mode, MeshScan scan, int allow_bits)
 {
     __shared__ MeshSmem<1, HaloMask> S;
     const Counters *c = m.ctr;
     const uint32_t epoch = c->dirty_epoch;
+    const int nslots = c->pool_used;
+    const bool bits = mode == 0 && allow_bits && c->bits_gap == 0 && nslots > m.bits_from &&
+                      (int)gridDim.x == m.bits_grid && (long long)nslots <= (long long)kThreads * 32 * gridDim.x;
     long long tris;
     int blocks;
-    mesh_count_wg(m, mode != 0, epoch, c->pool_used, S, &tris, &blocks, scan.rec + (size_t)blockIdx.x * scan.rec_cap,
-                  scan.wg_nz + blockIdx.x, scan.rec_cap);
+    mesh_count_wg(m, mode != 0, epoch, nslots, S, &tris, &blocks, scan.rec + (size_t)blockIdx.x * scan.rec_cap,
+                  scan.wg_nz + blockIdx.x, scan.rec_cap, bits);
     if (threadIdx.x == 0) {
         scan.wg_tris[blockIdx.x] = tris;
         scan.wg_blocks[blockIdx.x] = blocks;
-        if (blockIdx.x == 0) m.ctr->mesh_epoch = epoch;  // the emitting pass meshes this epoch
+        if (blockIdx.x == 0) {
+            m.ctr->mesh_epoch = epoch;  // the emitting pass meshes this epoch
+            m.ctr->mesh_bits = bits;
+        }
     }
 }
 
@@ -48,11 +58,11 @@ MeshGrid mesh_grid(int schedule)
 }
 
 hipError_t launch_mesh_count(const MapView &m, int mode, const MeshScan &scan, int schedule, MeshGrid grid,
-                             hipStream_t s)
+                             bool allow_bits, hipStream_t s)
 {
     if (grid.emit < 1 || grid.count < grid.emit || grid.count > kMaxMeshGrid || grid.count % grid.emit)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mesh_count, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan);
+    hipLaunchKernelGGL(k_mesh_count, dim3(grid.count), dim3(kThreads), 0, s, m, mode, scan, (int)allow_bits);
     return hipGetLastError();
 }
 

@@ -400,33 +400,18 @@ __device__ __forceinline__ int wave_scan_incl(int v)
     return v;
 }
 
-// One iteration's candidate slots of this workgroup, compacted into S.list in slot order;
-// returns their number, or -1 past the end.  Candidates are the map's slots [0, nslots),
-// dealt out one at a time: thread t of workgroup w takes slot (it kThreads + t) G + w,
-// so a cluster of dirty slots spreads over all workgroups.  A slot is taken if `all` or
-// its dirty mark (coordinates .w) holds `epoch`, and (need_tris: the emitting pass) the
-// counting pass found triangles in it.
+// The counting pass's candidates: the map's slots [0, nslots), dealt out one at a time,
+// thread t of workgroup w taking slot (q kThreads + t) G + w in round q, so that a cluster
+// of dirty slots spreads over all workgroups.  A slot is taken if `all` or its dirty mark
+// (coordinates .w) holds `epoch`.  Candidates reach the workgroup kThreads at a time,
+// compacted into S.list (slots) and S.lbc (coordinates).
+
+// Keep the round's slots that pass (one per thread), compacted in thread order; returns
+// their number.  The caller's reads of S.list are complete (a barrier follows the ballot).
 template <class Smem>
-__device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint32_t epoch, int nslots, int it,
-                                               bool need_tris, Smem &S)
+__device__ __forceinline__ int mesh_take(bool take, int slot, int4 bc, Smem &S)
 {
-    if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= nslots) return -1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long slot = ((long long)it * kThreads + threadIdx.x) * gridDim.x + blockIdx.x;
-    constexpr bool kKeep = !Smem::kEmit;  // the counting pass keeps the coordinates it reads
-    bool take = false;
-    int4 bc = make_int4(0, 0, 0, 0);
-    if (slot < nslots) {  // both loads issued together (the count is only used for dirty slots)
-        uint32_t fl;
-        if constexpr (kKeep) {
-            bc = m.coords[slot];
-            fl = (uint32_t)bc.w;
-        } else {
-            fl = (uint32_t)reinterpret_cast<const int *>(&m.coords[slot])[3];
-        }
-        const uint16_t nt = need_tris ? m.mesh_cnt[slot] : (uint16_t)1;
-        take = (all || fl == epoch) && nt != 0;
-    }
     const unsigned long long bal = __ballot(take);
     if (lane == 0) S.wcnt[wave] = __popcll(bal);
     __syncthreads();
@@ -439,11 +424,78 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
     }
     if (take) {
         const int at = off + __popcll(bal & ((1ull << lane) - 1ull));
-        S.list[at] = (int)slot;
-        if constexpr (kKeep) S.lbc[at] = bc;
+        S.list[at] = slot;
+        S.lbc[at] = bc;
     }
     __syncthreads();
     return n;
+}
+
+// Sweep of the slots: round `it`'s dirty candidates (or all of them), or -1 past the end.
+// The coordinates are read for every slot (their .w is the dirty mark).
+template <class Smem>
+__device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint32_t epoch, int nslots, int it, Smem &S)
+{
+    if (((long long)it * kThreads * gridDim.x + blockIdx.x) >= nslots) return -1;
+    const long long slot = ((long long)it * kThreads + threadIdx.x) * gridDim.x + blockIdx.x;
+    bool take = false;
+    int4 bc = make_int4(0, 0, 0, 0);
+    if (slot < nslots) {
+        bc = m.coords[slot];
+        take = all || (uint32_t)bc.w == epoch;
+    }
+    return mesh_take(take, (int)slot, bc, S);
+}
+
+// From the dirty bitmap instead (a DIRTY extraction of a large map): the workgroup's
+// slots w + j G are bits j of its own words of the bitmap, so thread t reads word t (bits
+// j = 32 t ...) and clears it, and the candidates cost one bitmap word per 32 slots and one
+// coordinate read per marked block, not a coordinate read per allocated slot.  Candidate i
+// of the workgroup (marked slots in j order, as the sweep would take them) goes to chunk
+// i / kThreads.  One word per thread: pools up to 8192 G blocks.
+struct BitCands {
+    uint32_t mask;  // bit b: slot w + (32 t + b) G is marked
+    int base;       // index of this thread's first candidate in the workgroup
+    int total;      // the workgroup's candidates
+};
+
+__device__ __forceinline__ BitCands mesh_bits_take(const MapView &m, int nslots, int *s_tmp)
+{
+    const int G = (int)gridDim.x, w = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int nj = nslots > w ? (nslots - w + G - 1) / G : 0;  // the workgroup's slots
+    uint32_t mask = 0;
+    if (t < (nj + 31) >> 5) {
+        uint32_t *word = &m.dbits[(size_t)w * m.bits_wpw + t];
+        mask = *word;
+        const int left = nj - 32 * t;  // slots of this word (bits past them are never set)
+        if (left < 32) mask &= (1u << left) - 1u;
+        *word = mask & 0u;  // cleared after the read returns (the store depends on it)
+    }
+    BitCands b;
+    b.mask = mask;
+    b.base = wg_scan(__popc(mask), s_tmp, &b.total);
+    return b;
+}
+
+template <class Smem>
+__device__ __forceinline__ int mesh_candidates_bits(const MapView &m, const BitCands &b, uint32_t epoch, int it,
+                                                    Smem &S)
+{
+    const int lo = it * kThreads;
+    if (lo >= b.total) return -1;
+    const long long G = gridDim.x;
+    uint32_t x = b.mask;
+    for (int idx = b.base; x && idx < lo + kThreads; ++idx) {  // this thread's candidates of the chunk
+        const int bit = __ffs(x) - 1;
+        x &= x - 1u;
+        if (idx >= lo) S.list[idx - lo] = (int)(blockIdx.x + (32ll * threadIdx.x + bit) * G);
+    }
+    __syncthreads();
+    const int n = b.total - lo < kThreads ? b.total - lo : kThreads;
+    const bool has = (int)threadIdx.x < n;
+    const int slot = has ? S.list[threadIdx.x] : 0;
+    const int4 bc = m.coords[slot];  // branch-free: slot 0 for threads past the chunk, unused
+    return mesh_take(has && (uint32_t)bc.w == epoch, slot, bc, S);  // a bit may outlive its mark
 }
 
 // Counting pass of one workgroup: triangles and blocks over its candidates, one
@@ -452,15 +504,18 @@ __device__ __forceinline__ int mesh_candidates(const MapView &m, bool all, uint3
 // slots) and their number is written to *nz, so the emitting pass reads them directly.
 __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32_t epoch, int nslots,
                                               MeshSmem<1, HaloMask> &S, long long *tris, int *blocks,
-                                              MeshRec *rec = nullptr, int32_t *nz = nullptr, int rec_cap = 0)
+                                              MeshRec *rec = nullptr, int32_t *nz = nullptr, int rec_cap = 0,
+                                              bool bits = false)
 {
     const TableRegs tab = mesh_tables_load<false>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     long long my_tris = 0;
     int my_blocks = 0, n_rec = 0;
     unsigned counts;
+    BitCands bcand{0u, 0, 0};
+    if (bits) bcand = mesh_bits_take(m, nslots, S.wcnt);
     for (int it = 0;; ++it) {
-        const int n = mesh_candidates(m, all, epoch, nslots, it, false, S);
+        const int n = bits ? mesh_candidates_bits(m, bcand, epoch, it, S) : mesh_candidates(m, all, epoch, nslots, it, S);
         if (it == 0) mesh_tables_store<false>(S, tab);
         if (n < 0) break;
         for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
@@ -520,63 +575,11 @@ __device__ __forceinline__ void mesh_count_wg(const MapView &m, bool all, uint32
     }
 }
 
-// Emitting pass of one workgroup: the same candidates in the same order, triangles from
-// output index `base` on.  A round is one block (kSched 0) or one block per wave
-// (kSched 1); a round's output is contiguous, in wave order.
-template <int kSched>
-__device__ __forceinline__ void mesh_emit_wg(const MapView &m, bool all, uint32_t epoch, int nslots, long long base,
-                                             const MeshOut &out, MeshSmem<kSched, HaloFull> &S, MeshStage &st,
-                                             const TableRegs &tab)
-{
-    constexpr int kPerRound = kSched == 0 ? 1 : kThreads / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rank = kSched == 0 ? (int)threadIdx.x : lane;
-    const int worker = kSched == 0 ? 0 : wave;
-    unsigned counts = 0;
-    long long carry = base;
-    for (int it = 0;; ++it) {
-        const int n = mesh_candidates(m, all, epoch, nslots, it, true, S);
-        if (it == 0) mesh_tables_store<true>(S, tab);
-        if (n < 0) break;
-        for (int j0 = 0; j0 < n; j0 += kMeshBatch) {
-            const int nb = n - j0 < kMeshBatch ? n - j0 : kMeshBatch;
-            mesh_batch_lookup(m, S, j0, nb);
-            for (int r = 0; r < nb; r += kPerRound) {
-                const int j = r + worker;
-                const bool has = j < nb;
-                int mine = 0;
-                if (kSched == 0) {
-                    mesh_stage<0>(m, S.nbs[j], S.h[0], rank);
-                    if (rank == 0) S.rbc[0] = S.bcs[j];
-                    mine = mesh_classify<0>(S.h[0], S.ntri, rank, S.ccase[0], &counts);
-                } else if (has) {
-                    mesh_stage_rows(m, S.nbs[j], S.h[worker], lane);
-                    if (lane == 0) S.rbc[worker] = S.bcs[j];
-                    mine = mesh_classify_rows(S.h[worker], S.ntri, lane, S.ccase[worker], &counts);
-                }
-                const int incl = wave_scan_incl(mine);
-                if (lane == 63) S.rcnt[wave] = incl;
-                __syncthreads();
-                int woff = 0, rtot = 0;
-#pragma unroll
-                for (int w = 0; w < kThreads / 64; ++w) {
-                    const int c = (int)S.rcnt[w];
-                    woff += w < wave ? c : 0;
-                    rtot += c;
-                }
-                mesh_round_out<kSched>(m, S, st, has, counts, woff + incl - mine, rtot, carry, out);
-                carry += rtot;
-                __syncthreads();  // the round's counts are rewritten by the next round
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // Emitting pass of one per-map workgroup from the counting pass's records: the blocks of
 // counting workgroups w + j G (j < k) in that order, batch by batch (each batch's records
-// read at once into the lookup arrays), triangles from output index `base` on.  Rounds as
-// in mesh_emit_wg.
+// read at once into the lookup arrays), triangles from output index `base` on.  A round is
+// one block (kSched 0) or one block per wave (kSched 1); a round's output is contiguous, in
+// wave order.
 template <int kSched>
 __device__ __forceinline__ void mesh_emit_recs(const MapView &m, const MeshScan &scan, int k, int my_nz,
                                                long long base, const MeshOut &out, MeshSmem<kSched, HaloFull> &S,
@@ -648,7 +651,9 @@ __device__ __forceinline__ void mesh_emit_recs(const MapView &m, const MeshScan 
 // 0) also sums every count and does the extraction's bookkeeping: totals, the epoch
 // advance that clears the dirty set when a DIRTY extraction fits (the counting pass has
 // read the epoch; the emitting pass meshes mesh_epoch, recorded by the counting pass),
-// and the host report, which therefore arrives while the rest of the pass still runs.
+// the dirty bitmap's gap flag (a DIRTY extraction that does not fit keeps the dirty set,
+// which the counting pass may have cleared from the bitmap), and the host report, which
+// therefore arrives while the rest of the pass still runs.
 __device__ __forceinline__ long long mesh_emit_base(const MapView &m, int mode, const long long *wg_tris,
                                                     const int32_t *wg_blocks, int g_count, long long cap,
                                                     MeshReport *report, long long *s_red)
@@ -708,7 +713,10 @@ __device__ __forceinline__ long long mesh_emit_base(const MapView &m, int mode, 
     if (lead && threadIdx.x == 0) {
         c->mesh_tris = (unsigned long long)total;
         c->mesh_blocks = (unsigned long long)blocks;
-        if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
+        if (mode == 0) {
+            if (total <= cap) c->dirty_epoch = epoch + 1;
+            c->bits_gap = total <= cap ? 0 : 1;  // a new epoch has no frame yet
+        }
         c->extractions = seq;
         if (report) {  // host memory: system-scope stores; the host waits for seq
             __hip_atomic_store(&report->tris, (unsigned long long)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -819,7 +827,10 @@ __device__ __forceinline__ void mesh_scan_map(const MapView &m, int mode, const 
         c->mesh_epoch = epoch;
         c->mesh_tris = (unsigned long long)total;
         c->mesh_blocks = (unsigned long long)blocks;
-        if (mode == 0 && total <= cap) c->dirty_epoch = epoch + 1;
+        if (mode == 0 && total <= cap) {
+            c->dirty_epoch = epoch + 1;
+            c->bits_gap = 0;  // a new epoch has no frame yet (set bits of older marks only cost work)
+        }
         c->extractions = seq;
         if (report) {  // host memory: system-scope stores; the host waits for seq, so it
                        // can return while the emitting pass still runs

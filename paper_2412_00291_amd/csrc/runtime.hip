@@ -35,6 +35,8 @@ struct map_s {
     uint32_t frame_id = 0;  // integration calls so far (tags hash insertions)
     int sched[3] = {0, 0, 0};  // TSDF, labels, meshing: 0 workgroup / 1 wavefront per block
     int tsdf_grid = 1024;      // TSDF workgroups: six per compute unit of the map's device
+    int64_t bits_user = -1;    // dirty-bitmap threshold set by the caller (< 0: the default)
+    bool bits_relaid = false;  // the bitmap's layout changed since the last DIRTY extraction
     std::string err;
     // LiDAR look-up tables (device) and the model they were built for
     float *lut_buf = nullptr;
@@ -76,6 +78,28 @@ struct map_s {
 };
 
 static std::string g_create_error;
+
+// Dirty bitmap words per counting workgroup for a counting grid of G workgroups.
+static int32_t bits_wpw(int64_t max_blocks, int G)
+{
+    return (int32_t)(((max_blocks + G - 1) / G + 31) / 32);
+}
+
+// The map's dirty-bitmap threshold and layout (MapView::bits_*): the caller's threshold,
+// or the pool size that one round of the counting pass's slot sweep covers (one slot per
+// thread of its grid); laid out for the counting grid of the current meshing schedule.
+// A new layout leaves the current epoch's marks behind: the next DIRTY extraction sweeps.
+static void set_bits(map_t *m)
+{
+    const int G = mesh_grid(m->sched[2]).count;
+    const long long d = m->bits_user >= 0 ? m->bits_user : (long long)kThreads * G;
+    m->v.bits_from = (int32_t)std::min<long long>(d, INT32_MAX);
+    if (m->v.bits_grid != G) {
+        m->v.bits_grid = G;
+        m->v.bits_wpw = bits_wpw(m->p.max_blocks, G);
+        m->bits_relaid = true;
+    }
+}
 
 // Partial sums of map_sdf_pose_adjoint_noalloc: a file-scope device array (each device the
 // library runs on holds its own copy until the process ends), so that call allocates
@@ -159,7 +183,7 @@ static void free_all(map_t *m)
     m->prof_pending.clear();
     m->prof_free.clear();
     void *ptrs[] = {m->v.dw, m->v.fused, m->v.counts, m->v.coords, m->v.hash,
-                    m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
+                    m->v.mesh_cnt, m->v.mesh_nbr, m->v.vmask, m->v.dbits, m->v.ctr, m->v.sync, m->f.fkeys, m->f.tk_key, m->f.tk_slot, m->f.tk_rank,
                     m->f.tk_fslot, m->f.band, m->f.nimg, m->f.rcopy, m->v.grad, m->v.logpost, m->lut_buf, m->partial,
                     m->scan.wg_tris, m->scan.wg_blocks, m->scan.wg_off, m->scan.rec, m->scan.wg_nz, m->rkeys};
     for (void *p : ptrs)
@@ -325,6 +349,13 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMalloc(&v.mesh_cnt, nb * sizeof(uint16_t)));
     CREATE_TRY(hipMalloc(&v.mesh_nbr, nb * 8 * sizeof(int32_t)));
     CREATE_TRY(hipMalloc(&v.vmask, nb * 16 * sizeof(unsigned long long)));
+    // the dirty bitmap, sized for the layout of either meshing schedule's counting grid
+    size_t bit_words = 0;
+    for (int sc = 0; sc < 2; ++sc) {
+        const int G = mesh_grid(sc).count;
+        bit_words = std::max(bit_words, (size_t)G * bits_wpw(p.max_blocks, G));
+    }
+    CREATE_TRY(hipMalloc(&v.dbits, bit_words * sizeof(uint32_t)));
     CREATE_TRY(hipMalloc(&v.ctr, sizeof(Counters)));
     CREATE_TRY(hipMalloc(&v.sync, sizeof(SyncState)));
     CREATE_TRY(hipMalloc(&m->scan.wg_tris, kMaxMeshGrid * sizeof(long long)));
@@ -343,6 +374,9 @@ extern "C" int map_create(const map_params *params, void *stream, map_t **out)
     CREATE_TRY(hipMemsetAsync(v.counts, 0, nb * (size_t)p.n_classes * kBlockVoxels * sizeof(uint16_t), s));
     CREATE_TRY(hipMemsetAsync(v.coords, 0, nb * sizeof(int4), s));
     CREATE_TRY(hipMemsetAsync(v.vmask, 0, nb * 16 * sizeof(unsigned long long), s));
+    CREATE_TRY(hipMemsetAsync(v.dbits, 0, bit_words * sizeof(uint32_t), s));
+    set_bits(m);
+    m->bits_relaid = false;  // no frame yet
     CREATE_TRY(hipMemsetAsync(v.sync, 0, sizeof(SyncState), s));
     CREATE_TRY(hipMemsetAsync(v.hash, 0xFF, hcap * sizeof(HashEntry), s));  // free keys, no insertion
     CREATE_TRY(launch_init_pool(v, s));
@@ -710,9 +744,10 @@ extern "C" int map_extract_mesh(map_t *m, int mode, float *pos_dev, uint8_t *lab
     const MeshGrid grid = mesh_grid(m->sched[2]);
     m->scan.rec_cap = (int32_t)((m->p.max_blocks + grid.count - 1) / grid.count + 256);
     HIP_TRY(m, timed(m, MAP_K_MESH, s, [&] {
-        hipError_t e = launch_mesh_count(m->v, mode, m->scan, m->sched[2], grid, s);
+        hipError_t e = launch_mesh_count(m->v, mode, m->scan, m->sched[2], grid, !m->bits_relaid, s);
         return e != hipSuccess ? e : launch_mesh_finish(m->v, mode, out, m->scan, m->d_report, m->sched[2], grid, s);
     }));
+    if (mode == MAP_MESH_DIRTY) m->bits_relaid = false;  // it swept; one that did not fit leaves the gap flag
     HIP_TRY(m, hipEventRecord(m->done, s));
     m->last_stream = s;
     const uint32_t seq = ++m->n_extract;
@@ -737,6 +772,16 @@ extern "C" int map_set_schedule(map_t *m, int32_t tsdf, int32_t labels, int32_t 
     for (int i = 0; i < 3; ++i)
         if (v[i] != 0 && v[i] != 1) return fail(m, MAP_ERR_INVALID_ARG, "set_schedule: schedules are 0 or 1");
     for (int i = 0; i < 3; ++i) m->sched[i] = v[i];
+    set_bits(m);  // the counting grid may differ between meshing schedules
+    return MAP_OK;
+}
+
+extern "C" int map_set_dirty_bitmap(map_t *m, int64_t min_blocks)
+{
+    if (!m) return MAP_ERR_INVALID_ARG;
+    FLUSH_PENDING(m);  // a pending frame keeps the threshold it was enqueued under
+    m->bits_user = min_blocks < 0 ? -1 : min_blocks;
+    set_bits(m);
     return MAP_OK;
 }
 
@@ -989,6 +1034,7 @@ extern "C" int map_stats(map_t *m, map_frame_stats *out)
     out->triangles = (int64_t)c.mesh_tris;
     out->allocated = c.pool_used;
     out->frames = c.frames;
+    out->mesh_from_bitmap = c.mesh_bits;
     return take_status(m);
 }
 

@@ -67,7 +67,7 @@ class _Quality(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("touched", "new_blocks", "updates", "votes", "mesh_blocks",
-                                              "triangles", "allocated", "frames")]
+                                              "triangles", "allocated", "frames", "mesh_from_bitmap")]
 
 
 _P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -93,6 +93,7 @@ _sig = {
     "map_read_block": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P, _P, _P]),
     "map_profile": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "map_set_schedule": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "map_set_dirty_bitmap": (ctypes.c_int, [_P, _I64]),
     "map_batch_create": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_P)]),
     "map_batch_configure": (ctypes.c_int, [_P, _I32, _I32, _I32]),
     "map_batch_step": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
@@ -520,6 +521,11 @@ class Map:
 
     def set_schedule(self, tsdf, labels, mesh):
         return self._check(_lib.map_set_schedule(self.h, int(tsdf), int(labels), int(mesh)))
+
+    def set_dirty_bitmap(self, min_blocks):
+        """Dirty meshing's candidates from the dirty bitmap above min_blocks allocated
+        blocks (< 0: the default threshold); see map_set_dirty_bitmap."""
+        return self._check(_lib.map_set_dirty_bitmap(self.h, int(min_blocks)))
 
     def profile(self, mask):
         return self._check(map_profile(self.h, mask))
