@@ -627,9 +627,10 @@ def bench_batched(torch, workers=None):
     return {"workload": "16 street maps, voxel 0.05-0.4 m, 16/32/64 x 1024-2048, "
                         f"{min(len(d[3]) for d in data)}-{max(len(d[3]) for d in data)} frames each, 1 camera",
             "steps_timed": n_steps - 1, "map_frames_timed": frames_timed,
-            "schedule": {"tsdf": ["workgroup-per-block", "wavefront-per-block"][sched & 1],
-                         "labels": ["workgroup-per-block", "wavefront-per-block"][sched >> 1],
-                         "meshing": "wavefront-per-block", "grid": grid},
+            "schedule": ({"tsdf": ["workgroup-per-block", "wavefront-per-block"][sched & 1],
+                          "labels": ["workgroup-per-block", "wavefront-per-block"][sched >> 1],
+                          "meshing": "wavefront-per-block", "grid": grid} if sched < 4 else
+                         {"concurrent": "each map's own kernels", "streams": grid}),
             "autotune_ms": {f"{k[0]},{k[1]}": 1e3 * v for k, v in timings.items()},
             "ms_per_step_batched": 1e3 * t_batch / (n_steps - 1),
             "ms_per_step_sequential": 1e3 * t_seq / (n_steps - 1),
@@ -704,6 +705,7 @@ def bench_campus(torch, warm=1500, timed=100, window=100, workers=None):
         if k >= warm:
             m.integrate_labels_multi(cams, labs, Tcs)
         m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+        torch.cuda.synchronize()  # the frame ends when its triangles are written
         t1 = time.perf_counter()
         for name, (a, b) in windows.items():
             if a <= k < b:

@@ -141,7 +141,7 @@ int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
 
 /* Work split of the per-map TSDF, label and meshing kernels (each 0 or 1): 0 = one
  * workgroup per block, 1 = one wavefront per block.  Results are identical either way;
- * only the speed differs.  Default 0, 0, 0. */
+ * only the speed differs.  Default 0, 0, 1. */
 int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
 
 /* Candidates of DIRTY meshing (Sec. IV-C.3: only the blocks changed since the last
@@ -292,10 +292,13 @@ typedef struct {
 } map_batch_item;
 
 int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out);
-/* schedule: bit 0 for the TSDF phase, bit 1 for the label phase, each 0 = one workgroup
- * per touched block, 1 = one wavefront per touched block (so 0..3); grid: workgroups of
- * those phases (64..4096); use_graph: capture each step shape once in a hipGraph and
- * replay it.  Returns MAP_ERR_INVALID_ARG for values out of range. */
+/* schedule 0..3: one launch per phase for all maps; bit 0 for the TSDF phase, bit 1 for
+ * the label phase, each 0 = one workgroup per touched block, 1 = one wavefront per touched
+ * block; grid: workgroups of those phases (64..4096); use_graph: capture each step shape
+ * once in a hipGraph and replay it.  schedule 4: each map's own kernels, as its plain calls
+ * launch them (with its own schedules), the maps dealt over `grid` streams (1..16) of the
+ * batch that run concurrently between the caller's stream's earlier and later work
+ * (use_graph ignored).  Returns MAP_ERR_INVALID_ARG for values out of range. */
 int map_batch_configure(map_batch_t *batch, int32_t schedule, int32_t grid, int32_t use_graph);
 int map_batch_step(map_batch_t *batch, const map_batch_item *items, int32_t n_items, int64_t *n_tris,
                    void *stream);

@@ -1,5 +1,6 @@
-"""Autotuner of the batched step's schedule (one workgroup or one wavefront per touched
-block in the TSDF and label phases) and persistent grid size.
+"""Autotuner of the batched step's schedule (one launch per phase with one workgroup or one
+wavefront per touched block in the TSDF and label phases, and its grid size; or each map's
+own kernels over several streams, and their number).
 
 Each candidate runs the same frames on freshly created maps (the maps are mutated by a
 step, so candidates never share them); the step times after the first (which also sizes
@@ -12,9 +13,10 @@ import json
 import os
 import time
 
-# (schedule, grid): schedule bit 0 = TSDF, bit 1 = labels, each 0 workgroup / 1 wavefront
-# per touched block
-CANDIDATES = [(s, g) for s in (0, 1, 2, 3) for g in (1024, 2048, 4096)]
+# (schedule, grid): schedules 0..3 run one launch per phase (bit 0 = TSDF, bit 1 = labels,
+# each 0 workgroup / 1 wavefront per touched block) on a grid of that many workgroups;
+# schedule 4 runs each map's own kernels with the maps spread over `grid` streams
+CANDIDATES = [(s, g) for s in (0, 1, 2, 3) for g in (1024, 2048, 4096)] + [(4, k) for k in (2, 4, 8)]
 
 
 def cache_path():

@@ -243,6 +243,8 @@ __device__ inline int hash_find(const MapView &m, unsigned long long key)
 // batched steps: one launch per phase covers every map of the step
 // ---------------------------------------------------------------------------------
 constexpr int kMaxBatchMaps = 64;
+constexpr int kBatchConcurrent = 4;   // batch schedule: each map's own kernels, maps over several streams
+constexpr int kMaxBatchStreams = 16;  // streams of that schedule
 
 struct BatchMap {  // one map's frame in a batched step (device array, refreshed per step)
     MapView v;

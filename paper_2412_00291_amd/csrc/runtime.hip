@@ -33,7 +33,7 @@ struct map_s {
     bool has_scan = false;
     MeshScan scan{};        // extraction scratch, kMaxMeshGrid workgroups
     uint32_t frame_id = 0;  // integration calls so far (tags hash insertions)
-    int sched[3] = {0, 0, 0};  // TSDF, labels, meshing: 0 workgroup / 1 wavefront per block
+    int sched[3] = {0, 0, 1};  // TSDF, labels, meshing: 0 workgroup / 1 wavefront per block
     int tsdf_grid = 1024;      // TSDF workgroups: six per compute unit of the map's device
     int64_t bits_user = -1;    // dirty-bitmap threshold set by the caller (< 0: the default)
     bool bits_relaid = false;  // the bitmap's layout changed since the last DIRTY extraction
@@ -1179,6 +1179,11 @@ struct map_batch_s {
     bool use_graph = true;
     // one executable graph per step shape (map count, tile count, schedule, grid, stream)
     std::map<std::tuple<int, int, int, int, hipStream_t>, hipGraphExec_t> graphs;
+    // the concurrent schedule: streams the maps' own kernel chains are spread over, and the
+    // events that fork them from and join them to the caller's stream
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
     std::string err;
 };
 
@@ -1186,6 +1191,11 @@ static void batch_free(map_batch_t *b)
 {
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
     b->graphs.clear();
+    for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    b->streams.clear();
+    b->joins.clear();
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_ctl) (void)hipFree(b->d_ctl);
     void *ptrs[] = {b->d_sync, b->scan.wg_tris, b->scan.wg_blocks, b->scan.wg_off};
@@ -1242,11 +1252,56 @@ extern "C" int map_batch_create(map_t *const *maps, int32_t n, map_batch_t **out
 
 extern "C" int map_batch_configure(map_batch_t *b, int32_t schedule, int32_t grid, int32_t use_graph)
 {
-    if (!b || schedule < 0 || schedule > 3 || grid < 64 || grid > kMaxMeshGrid) return MAP_ERR_INVALID_ARG;
+    if (!b || schedule < 0 || schedule > kBatchConcurrent) return MAP_ERR_INVALID_ARG;
+    if (schedule == kBatchConcurrent ? (grid < 1 || grid > kMaxBatchStreams) : (grid < 64 || grid > kMaxMeshGrid))
+        return MAP_ERR_INVALID_ARG;
+    if (schedule == kBatchConcurrent) {  // its streams and events, created once
+        if (hipSetDevice(b->device) != hipSuccess) return MAP_ERR_DEVICE;
+        if (!b->fork && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return MAP_ERR_DEVICE;
+        while ((int)b->streams.size() < grid) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return MAP_ERR_DEVICE;
+            b->streams.push_back(st);
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return MAP_ERR_DEVICE;
+            b->joins.push_back(ev);
+        }
+    }
     b->schedule = schedule;
     b->grid = grid;
     b->use_graph = use_graph != 0;
     return MAP_OK;
+}
+
+// The concurrent schedule of a step: each map's own kernels (allocation, TSDF with its
+// camera labels fused, the two meshing passes), exactly as its plain calls launch them,
+// the maps dealt round-robin over the batch's streams so that their latency-bound chains
+// overlap; the streams wait for the caller's stream first and it waits for them after.
+static hipError_t launch_concurrent(map_batch_t *b, const map_batch_item *items, int n, hipStream_t s)
+{
+    const int K = std::min(b->grid, n);
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->streams[k], b->fork, 0);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        map_t *m = b->maps[items[i].map_index];
+        const BatchMap &d = b->h_desc[i];
+        const hipStream_t sk = b->streams[i % K];
+        e = launch_alloc(m->v, m->f, m->lut, d.T, d.range, m->dist_mode, m->cos_inc, sk);
+        if (e == hipSuccess)
+            e = launch_tsdf(m->v, m->f, m->lut, d.T, m->f.rcopy, d.frame_id, m->sched[0],
+                            grid_for(m->f.tk_cap, 1, m->tsdf_grid), m->dist_mode, d.cams, m->label_mode, sk);
+        const MeshGrid grid = mesh_grid(m->sched[2]);
+        m->scan.rec_cap = (int32_t)((m->p.max_blocks + grid.count - 1) / grid.count + 256);
+        if (e == hipSuccess) e = launch_mesh_count(m->v, 0, m->scan, m->sched[2], grid, !m->bits_relaid, sk);
+        m->bits_relaid = false;
+        if (e == hipSuccess) e = launch_mesh_finish(m->v, 0, d.out, m->scan, b->d_reports + i, m->sched[2], grid, sk);
+        m->last_stream = sk;
+    }
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+        e = hipEventRecord(b->joins[k], b->streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->joins[k], 0);
+    }
+    return e;
 }
 
 extern "C" void map_batch_destroy(map_batch_t *b)
@@ -1329,9 +1384,14 @@ extern "C" int map_batch_step(map_batch_t *b, const map_batch_item *items, int32
     // Report slots follow item order, so clear their sequence numbers (no device write to
     // them is pending: the previous step returned after all of its reports).
     for (int i = 0; i < n; ++i) __atomic_store_n(&b->h_reports[i].seq, 0ull, __ATOMIC_RELEASE);
-    hipError_t e = hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(BatchMap), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return fail_b(e, "descriptor upload");
-    if (b->use_graph && s != nullptr) {  // the legacy default stream cannot be captured
+    hipError_t e = hipSuccess;
+    if (b->schedule == kBatchConcurrent) {
+        e = launch_concurrent(b, items, n, s);
+        if (e != hipSuccess) return fail_b(e, "concurrent launch");
+    } else if ((e = hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(BatchMap), hipMemcpyHostToDevice, s)) !=
+               hipSuccess) {
+        return fail_b(e, "descriptor upload");
+    } else if (b->use_graph && s != nullptr) {  // the legacy default stream cannot be captured
         const auto key = std::make_tuple(n, tiles, b->schedule, b->grid, s);
         auto itg = b->graphs.find(key);
         if (itg == b->graphs.end()) {

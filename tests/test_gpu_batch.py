@@ -143,7 +143,7 @@ def _run_batched(torch, data, schedule, grid):
     return maps, batch, digests
 
 
-@pytest.mark.parametrize("schedule,grid", [(0, 2048), (1, 1024), (2, 4096), (3, 1024)])
+@pytest.mark.parametrize("schedule,grid", [(0, 2048), (1, 1024), (2, 4096), (3, 1024), (4, 4)])
 def test_batched_equals_plain_calls_and_oracle(torch_dev_batch, batch_data, sequential, schedule, grid):
     torch = torch_dev_batch
     seq_maps, seq_digests = sequential

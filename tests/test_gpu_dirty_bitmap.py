@@ -69,7 +69,7 @@ def test_bitmap_equals_sweep_and_oracle(torch_mod):
         if k == 5:
             m_bits.set_dirty_bitmap(NEVER)  # this frame's marks stay out of the bitmap
         if k == 7:
-            m_bits.set_schedule(0, 0, 1)    # the counting grid (and the layout) may change
+            m_bits.set_schedule(0, 0, 0)    # the counting grid (and the layout) may change
         for m in (m_bits, m_sweep):
             m.integrate_lidar(lid, rng, f.T_wl)
             m.integrate_labels(cam, labd, T)
