@@ -205,6 +205,7 @@ def _cpu_run(w, frames, budget_s, variant):
     U = 0
     t_total = 0.0
     n = 0
+    per_frame = []
     for k, f in enumerate(frames):
         t0 = time.perf_counter()
         om.integrate_lidar(w.lidar, f.range, f.T_wl)
@@ -212,12 +213,14 @@ def _cpu_run(w, frames, budget_s, variant):
             om.integrate_labels(cam, lab, T)
         om.extract_mesh(oracle.MESH_DIRTY, with_keys=False)
         t_total += time.perf_counter() - t0
-        U += om.stats()["updates"]
+        s = om.stats()
+        per_frame.append(s)
+        U += s["updates"]
         n += 1
         if t_total >= budget_s:
             break
     om.close()
-    return U / t_total, 1e3 * t_total / n, n
+    return U / t_total, 1e3 * t_total / n, n, per_frame
 
 
 def cpu_baseline(w, frames, budget_s):
@@ -226,9 +229,9 @@ def cpu_baseline(w, frames, budget_s):
     blocks in parallel, identical results) and its plain single-threaded build."""
     import oracle
     threads = oracle.threads("omp")
-    v_omp, ms_omp, n_omp = _cpu_run(w, frames, budget_s, "omp")
-    v_one, ms_one, n_one = _cpu_run(w, frames, budget_s, "plain")
-    return {"value": v_omp, "unit": "voxel-updates/s", "cores": threads, "kind": "oracle",
+    v_omp, ms_omp, n_omp, per_frame = _cpu_run(w, frames, budget_s, "omp")
+    v_one, ms_one, n_one, _ = _cpu_run(w, frames, budget_s, "plain")
+    return per_frame, {"value": v_omp, "unit": "voxel-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"street frames 0-{n_omp - 1} of the same sequence, whole path per frame "
                       f"(scan + 4 label images + dirty mesh), OpenMP build on {threads} threads",
             "ms_per_frame": ms_omp, "frames": n_omp,
@@ -957,7 +960,13 @@ def main():
                                 "large_scale": bench_campus(torch)}
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_baseline_seconds)
+        oracle_frames, result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_baseline_seconds)
+        # the per-frame counts behind `value` (the GPU counting pass) against the oracle's
+        keys = ("updates", "votes", "touched", "new_blocks", "mesh_blocks", "triangles", "allocated")
+        bad = [(k, key, per_frame[k][key], o[key]) for k, o in enumerate(oracle_frames) for key in keys
+               if per_frame[k][key] != o[key]]
+        result["oracle_check"] = {"frames": len(oracle_frames), "counts": list(keys), "equal": not bad,
+                                  "mismatches": bad[:5]}
     print(json.dumps(result))
 
 

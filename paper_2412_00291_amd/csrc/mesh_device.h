@@ -469,7 +469,7 @@ __device__ __forceinline__ BitCands mesh_bits_take(const MapView &m, int nslots,
         mask = *word;
         const int left = nj - 32 * t;  // slots of this word (bits past them are never set)
         if (left < 32) mask &= (1u << left) - 1u;
-        *word = mask & 0u;  // cleared after the read returns (the store depends on it)
+        *word = 0u;  // a thread's load and later store of one address keep their order
     }
     BitCands b;
     b.mask = mask;

@@ -1275,17 +1275,33 @@ extern "C" int map_batch_configure(map_batch_t *b, int32_t schedule, int32_t gri
 
 // The concurrent schedule of a step: each map's own kernels (allocation, TSDF with its
 // camera labels fused, the two meshing passes), exactly as its plain calls launch them,
-// the maps dealt round-robin over the batch's streams so that their latency-bound chains
-// overlap; the streams wait for the caller's stream first and it waits for them after.
+// the maps spread over the batch's streams so that their latency-bound chains overlap:
+// largest first, each to the stream with the least work so far, a map's work taken as its
+// scan's pixels over its voxel area (the blocks a frame touches grow with both).  The
+// streams wait for the caller's stream first and it waits for them after.
 static hipError_t launch_concurrent(map_batch_t *b, const map_batch_item *items, int n, hipStream_t s)
 {
     const int K = std::min(b->grid, n);
+    std::vector<double> work(n), load(K, 0.0);
+    std::vector<int> order(n), stream_of(n);
+    for (int i = 0; i < n; ++i) {
+        const double nu = b->maps[items[i].map_index]->p.voxel_size;
+        work[i] = (double)items[i].lidar->rows * items[i].lidar->cols / (nu * nu);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        stream_of[i] = k;
+        load[k] += work[i];
+    }
     hipError_t e = hipEventRecord(b->fork, s);
     for (int k = 0; k < K && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->streams[k], b->fork, 0);
-    for (int i = 0; i < n && e == hipSuccess; ++i) {
+    for (int j = 0; j < n && e == hipSuccess; ++j) {
+        const int i = order[j];
         map_t *m = b->maps[items[i].map_index];
         const BatchMap &d = b->h_desc[i];
-        const hipStream_t sk = b->streams[i % K];
+        const hipStream_t sk = b->streams[stream_of[i]];
         e = launch_alloc(m->v, m->f, m->lut, d.T, d.range, m->dist_mode, m->cos_inc, sk);
         if (e == hipSuccess)
             e = launch_tsdf(m->v, m->f, m->lut, d.T, m->f.rcopy, d.frame_id, m->sched[0],
