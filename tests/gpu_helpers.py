@@ -8,9 +8,13 @@ import oracle
 
 
 def step_log(msg):
-    """Append a progress line to the output folder's steps.log (names the step before it runs)."""
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "steps.log"), "a") as fh:
+    """Append a progress line (naming the step before it runs) to the file that
+    $MAPCORE_STEP_LOG names, if it is set."""
+    path = os.environ.get("MAPCORE_STEP_LOG")
+    if not path:
+        return
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    with open(path, "a") as fh:
         fh.write(f"{time.strftime('%H:%M:%S')} {msg}\n")
 
 
