@@ -162,10 +162,6 @@ __device__ __forceinline__ void mesh_stage(const MapView &m, const int *nb, Halo
     worker_sync<kSched>();
 }
 
-// Cases of the lane's cubes (cube it * kWidth + rank): returns the lane's triangles,
-// packs each cube's triangle count into 4 bits of *counts, and stores each cube's case
-// in ccase[cube] when ccase is given.  A cube counts only when all eight corners are
-// observed (W > 0).
 // Stage a halo by rows (one wavefront): lane l takes rows l and l + 64.  A row's 8
 // voxels of one block are 64 contiguous bytes (four 16-byte loads), the 9th is the first
 // voxel of the +x neighbour's row; both blocks' loads are issued before either is used,
@@ -267,6 +263,10 @@ __device__ __forceinline__ int mesh_classify_rows(const Halo &S, const uint8_t *
     return mine;
 }
 
+// Cases of the lane's cubes (cube it * kWidth + rank): returns the lane's triangles,
+// packs each cube's triangle count into 4 bits of *counts, and stores each cube's case
+// in ccase[cube] when ccase is given.  A cube counts only when all eight corners are
+// observed (W > 0).
 template <int kSched, class Halo>
 __device__ __forceinline__ int mesh_classify(const Halo &S, const uint8_t *ntri, int rank, uint8_t *ccase,
                                              unsigned *counts)
