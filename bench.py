@@ -796,6 +796,8 @@ def bench_campus_fine(torch, w, lid, frames, warm, window):
                 s = m.stats()[1]
                 from_bits += s["mesh_from_bitmap"]
                 blocks += s["mesh_blocks"]
+            if (k + 1) % 100 == 0:
+                log(f"[bench] campus at 0.05 m, {name}: frame {k + 1}/{warm}")
         torch.cuda.synchronize()
         ms, launches = m.profile_read()["mesh"]
         out[name] = {"allocated_blocks_start": a0, "allocated_blocks_end": m.stats()[1]["allocated"],
