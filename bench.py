@@ -755,6 +755,7 @@ def bench_campus(torch, warm=1300, timed=200, window=100, workers=None):
         if (k + 1) % 100 == 0:
             log(f"[bench] campus: frame {k + 1}/{n}")
     m.close()
+    same = campus_same_frames(torch, w, lid, frames, pos, lab, window)
     del pos, lab
     fine = bench_campus_fine(torch, w, lid, frames, warm, window)
     t = np.array(times) * 1e3
@@ -764,7 +765,41 @@ def bench_campus(torch, warm=1300, timed=200, window=100, workers=None):
             "ms_per_frame_p90": float(np.percentile(t, 90)), "voxel_updates_per_s": U / (t.sum() * 1e-3),
             "mesh_blocks_per_frame": float(np.mean(mesh_blocks)),
             "allocated_blocks_start": int(alloc[0]), "allocated_blocks_end": int(alloc[-1]),
-            "mesh_windows": win, "fine_voxels": fine}
+            "mesh_windows": win, "mesh_same_frames": same, "fine_voxels": fine}
+
+
+def campus_same_frames(torch, w, lid, frames, pos, lab, window):
+    """Meshing of the same frames in a small and in a larger map: frames 0..399 (scan and
+    dirty meshing) into a fresh map, and into a map that first took frames 900..1299 (the
+    far side of the loop, beyond the scan's range from frames 300..399, so the dirty blocks
+    of those frames are the same blocks in both maps); meshing timed with events over
+    frames 300..399 in each."""
+    from paper_2412_00291_amd import KERNEL_NAMES, Map, MAP_MESH_DIRTY
+    mesh_mask = 1 << KERNEL_NAMES.index("mesh")
+    first = 400 - window
+    out = {"frames_timed": f"{first}-399"}
+    for name, pre in (("small", []), ("large", list(range(900, 1300)))):
+        m = Map(w.voxel, w.trunc, w.n_classes, w.max_blocks)
+        for k in pre:
+            m.integrate_lidar(lid, frames[k][0], w.poses[k])
+            m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+        blocks = 0
+        for k in range(400):
+            if k == first:
+                torch.cuda.synchronize()
+                m.profile(mesh_mask)
+                a0 = m.stats()[1]["allocated"]
+            m.integrate_lidar(lid, frames[k][0], w.poses[k])
+            m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+            if k >= first:
+                blocks += m.stats()[1]["mesh_blocks"]
+        torch.cuda.synchronize()
+        ms, launches = m.profile_read()["mesh"]
+        out[name] = {"allocated_blocks_start": a0, "allocated_blocks_end": m.stats()[1]["allocated"],
+                     "mesh_us_per_frame": 1e3 * ms / launches, "mesh_blocks_per_frame": blocks / launches}
+        m.close()
+        log(f"[bench] campus, same frames in the {name} map: {out[name]}")
+    return out
 
 
 def bench_campus_fine(torch, w, lid, frames, warm, window):
