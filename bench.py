@@ -597,7 +597,7 @@ def bench_batched(torch, workers=None):
             batch.step(items_for(k))
 
     sig = "street16-seed3-real-" + "-".join(str(len(d[3])) for d in data)
-    sched, grid, timings = autotune.tune(sig, build, run_step, n_steps=2)
+    sched, grid, timings = autotune.tune(sig, build, run_step, n_steps=6)
     log(f"[bench] batched: autotuner chose schedule {sched}, grid {grid}")
 
     # batched, all steps (items prepared beforehand, as a caller holding its frames would);
