@@ -16,7 +16,7 @@ import time
 # (schedule, grid): schedules 0..3 run one launch per phase (bit 0 = TSDF, bit 1 = labels,
 # each 0 workgroup / 1 wavefront per touched block) on a grid of that many workgroups;
 # schedule 4 runs each map's own kernels with the maps spread over `grid` streams
-CANDIDATES = [(s, g) for s in (0, 1, 2, 3) for g in (1024, 2048, 4096)] + [(4, k) for k in (2, 4, 8)]
+CANDIDATES = [(s, g) for s in (0, 1, 2, 3) for g in (1024, 2048, 4096)] + [(4, k) for k in (2, 4, 8, 16)]
 
 
 def cache_path():
