@@ -247,21 +247,54 @@ def _cpu_run(w, frames, budget_s, variant):
     return U / t_total, 1e3 * t_total / n, n, per_frame
 
 
-def cpu_baseline(w, frames, budget_s):
+def campus_oracle(campus):
+    """The oracle's OpenMP build on the first campus frames (scan, both label images, dirty
+    meshing; room for 200K blocks as on the GPU): each frame's counts against the GPU's, and
+    its time per frame on this host."""
+    import oracle
+    w, host, gpu = campus
+    n = len(host)
+    om = oracle.OracleMap(w.voxel, w.trunc, w.n_classes, CAMPUS_CHECK_BLOCKS, variant="omp")
+    cpu, t = [], 0.0
+    for k in range(n):
+        rng, labs, Tcs = host[k]
+        t0 = time.perf_counter()
+        om.integrate_lidar(w.lidar, rng, w.poses[k])
+        for c, l, T in zip(w.cameras, labs, Tcs):
+            om.integrate_labels(c, l, T)
+        om.extract_mesh(oracle.MESH_DIRTY, with_keys=False)
+        t += time.perf_counter() - t0
+        cpu.append(om.stats())
+    om.close()
+    keys = ("updates", "votes", "touched", "new_blocks", "mesh_blocks", "triangles", "allocated")
+    bad = [(k, key, gpu[k][key], cpu[k][key]) for k in range(n) for key in keys if gpu[k][key] != cpu[k][key]]
+    U = sum(s["updates"] for s in cpu)
+    return ({"frames": n, "counts": list(keys), "equal": not bad, "mismatches": bad[:5]},
+            {"value": U / t, "unit": "voxel-updates/s", "cores": oracle.threads("omp"), "ms_per_frame": 1e3 * t / n,
+             "sample": f"campus frames 0-{n - 1} (128x2048 scan, 2 x 1920x1080 label images, dirty mesh), "
+                       "OpenMP build"})
+
+
+def cpu_baseline(w, frames, budget_s, campus=None):
     """The oracle on this host's cores, whole path per frame, on the first frames of the same
     sequence: its OpenMP build (every host thread; loops over rows, touched blocks and meshed
-    blocks in parallel, identical results) and its plain single-threaded build."""
+    blocks in parallel, identical results) and its plain single-threaded build; with
+    `campus`, also the first campus frames, checked against the GPU's counts."""
     import oracle
     threads = oracle.threads("omp")
     v_omp, ms_omp, n_omp, per_frame = _cpu_run(w, frames, budget_s, "omp")
     v_one, ms_one, n_one, _ = _cpu_run(w, frames, budget_s, "plain")
-    return per_frame, {"value": v_omp, "unit": "voxel-updates/s", "cores": threads, "kind": "oracle",
+    extra = {}
+    if campus is not None:
+        extra["campus_check"], extra["campus"] = campus_oracle(campus)
+    return per_frame, extra, {"value": v_omp, "unit": "voxel-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"street frames 0-{n_omp - 1} of the same sequence, whole path per frame "
                       f"(scan + 4 label images + dirty mesh), OpenMP build on {threads} threads",
             "ms_per_frame": ms_omp, "frames": n_omp,
             "single_thread": {"value": v_one, "unit": "voxel-updates/s", "cores": 1, "ms_per_frame": ms_one,
                               "frames": n_one, "sample": f"street frames 0-{n_one - 1}, plain build"},
-            "cpu": _cpu_model(), "host_threads_available": len(os.sched_getaffinity(0))}
+            "cpu": _cpu_model(), "host_threads_available": len(os.sched_getaffinity(0)),
+            **({"campus": extra["campus"]} if "campus" in extra else {})}
 
 
 def _cpu_model():
@@ -683,7 +716,7 @@ def _campus_frame(args):
     return k, f.range, [np.ascontiguousarray(l) for _, l, _ in f.cams], [T for T, _, _ in f.cams]
 
 
-def bench_campus(torch, warm=1300, timed=200, window=100, workers=None):
+def bench_campus(torch, warm=1300, timed=200, window=100, n_check=30, workers=None):
     """Large-scale form: 128x2048 scans and two 1920x1080 cameras on the campus loop, in a
     map with room for 2M blocks (~50 GB).  Frames 0..warm-1 grow the map (scan and dirty
     meshing; no labels); meshing alone is timed with events over two windows of the growth,
@@ -703,9 +736,12 @@ def bench_campus(torch, warm=1300, timed=200, window=100, workers=None):
     t0 = time.time()
     frames = {}
     with mp.get_context("spawn").Pool(workers) as pool:
-        jobs = [(k, n, k >= warm) for k in range(n)]
+        jobs = [(k, n, k >= warm or k < n_check) for k in range(n)]
+        host = {}
         for k, rng, labs, Tcs in pool.imap_unordered(_campus_frame, jobs, chunksize=4):
             frames[k] = (torch.from_numpy(rng).cuda(), [torch.from_numpy(l).cuda() for l in labs], Tcs)
+            if k < n_check:
+                host[k] = (rng, labs, Tcs)
             if len(frames) % 100 == 0:
                 log(f"[bench] campus: {len(frames)}/{n} frames generated ({time.time() - t0:.0f} s)")
     torch.cuda.synchronize()
@@ -756,6 +792,7 @@ def bench_campus(torch, warm=1300, timed=200, window=100, workers=None):
             log(f"[bench] campus: frame {k + 1}/{n}")
     m.close()
     same = campus_same_frames(torch, w, lid, frames, pos, lab, window)
+    check = (w, host, campus_gpu_counts(torch, w, lid, cams, frames, len(host), pos, lab))
     del pos, lab
     fine = bench_campus_fine(torch, w, lid, frames, warm, window)
     t = np.array(times) * 1e3
@@ -765,7 +802,27 @@ def bench_campus(torch, warm=1300, timed=200, window=100, workers=None):
             "ms_per_frame_p90": float(np.percentile(t, 90)), "voxel_updates_per_s": U / (t.sum() * 1e-3),
             "mesh_blocks_per_frame": float(np.mean(mesh_blocks)),
             "allocated_blocks_start": int(alloc[0]), "allocated_blocks_end": int(alloc[-1]),
-            "mesh_windows": win, "mesh_same_frames": same, "fine_voxels": fine}
+            "mesh_windows": win, "mesh_same_frames": same, "fine_voxels": fine}, check
+
+
+def campus_gpu_counts(torch, w, lid, cams, frames, n, pos, lab):
+    """The first campus frames (scan, both label images, dirty meshing) on the GPU into a map
+    with room for 200K blocks: each frame's counts, for the CPU baseline's oracle run on the
+    same frames to compare."""
+    from paper_2412_00291_amd import Map, MAP_MESH_DIRTY
+    m = Map(w.voxel, w.trunc, w.n_classes, CAMPUS_CHECK_BLOCKS)
+    out = []
+    for k in range(n):
+        r, labs, Tcs = frames[k]
+        m.integrate_lidar(lid, r, w.poses[k])
+        m.integrate_labels_multi(cams, labs, Tcs)
+        m.extract_mesh(MAP_MESH_DIRTY, pos, lab, None)
+        out.append(m.stats()[1])
+    m.close()
+    return out
+
+
+CAMPUS_CHECK_BLOCKS = 200_000
 
 
 def campus_same_frames(torch, w, lid, frames, pos, lab, window):
@@ -1013,16 +1070,20 @@ def main():
         "roofline_groups": roofline_groups,
         "h2d_inputs": h2d_inputs(torch, frames),
     }
+    campus = None  # the first campus frames' inputs and GPU counts, for the oracle check
     if not args.no_extensions:
         result["extensions"] = {"pose_adjoint": bench_adjoint(torch), "range_image": bench_range_image(torch),
                                 "lidar_labels": bench_lidar_labels(torch),
                                 "nonprojective": bench_nonprojective(torch),
                                 "label_modes": bench_label_modes(torch),
                                 "batched": bench_batched(torch),
-                                "large_scale": bench_campus(torch)}
+                                "large_scale": None}
+        result["extensions"]["large_scale"], campus = bench_campus(torch)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        oracle_frames, result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_baseline_seconds)
+        oracle_frames, extra, result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_baseline_seconds, campus)
+        if "campus_check" in extra:
+            result["oracle_check_campus"] = extra["campus_check"]
         # the per-frame counts behind `value` (the GPU counting pass) against the oracle's
         keys = ("updates", "votes", "touched", "new_blocks", "mesh_blocks", "triangles", "allocated")
         bad = [(k, key, per_frame[k][key], o[key]) for k, o in enumerate(oracle_frames) for key in keys
