@@ -560,6 +560,12 @@ def bench_label_modes(torch, frames=12, warm=2):
 _BATCHED = {}
 
 
+def _one_thread_worker():
+    """Frame-generation workers each ray-cast on one thread (the pool supplies the
+    parallelism; an OpenMP team per worker would oversubscribe the host)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+
+
 def _batched_frame(args):
     """One frame of one batched map (worker process): (m, k, range, T_wl, label image, T_wc)."""
     import synth
@@ -592,7 +598,7 @@ def bench_batched(torch, workers=None):
     jobs = [(m, k) for m, w in enumerate(ws) for k in range(w.n_frames)]
     frames = [[None] * w.n_frames for w in ws]
     t0 = time.time()
-    with mp.get_context("spawn").Pool(workers) as pool:
+    with mp.get_context("spawn").Pool(workers, initializer=_one_thread_worker) as pool:
         for i, (m, k, r, T, lab, Tc) in enumerate(pool.imap_unordered(_batched_frame, jobs, chunksize=8)):
             frames[m][k] = (torch.from_numpy(r).cuda(), T, torch.from_numpy(lab).cuda(), Tc)
             if (i + 1) % 500 == 0:
@@ -735,7 +741,7 @@ def bench_campus(torch, warm=1300, timed=200, window=100, n_check=30, workers=No
     workers = workers or min(16, len(os.sched_getaffinity(0)))
     t0 = time.time()
     frames = {}
-    with mp.get_context("spawn").Pool(workers) as pool:
+    with mp.get_context("spawn").Pool(workers, initializer=_one_thread_worker) as pool:
         jobs = [(k, n, k >= warm or k < n_check) for k in range(n)]
         host = {}
         for k, rng, labs, Tcs in pool.imap_unordered(_campus_frame, jobs, chunksize=4):

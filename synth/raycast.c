@@ -39,6 +39,7 @@ typedef struct {
     double hf_x0, hf_y0, hf_h;
     int hf_nx, hf_ny;
     float *hf_z;
+    double hf_zmax; /* highest lattice node: a ray above it and not descending hits no cell */
     /* grid */
     double gx0, gy0, gcell;
     int gnx, gny;
@@ -129,6 +130,8 @@ void synth_scene_set_heightfield(void *sp, double x0, double y0, double h, int n
     free(s->hf_z);
     s->hf_z = (float *)malloc((size_t)nx * ny * sizeof(float));
     memcpy(s->hf_z, z, (size_t)nx * ny * sizeof(float));
+    s->hf_zmax = -INFINITY;
+    for (size_t q = 0; q < (size_t)nx * ny; ++q) s->hf_zmax = dmax(s->hf_zmax, (double)z[q]);
     s->ground_kind = 2;
 }
 
@@ -323,6 +326,9 @@ static double hit_heightfield(const scene *s, const double *p, const double *d, 
     double ty = d[1] != 0 ? ((sj > 0 ? (j + 1 - gy) : (gy - j)) * h) / fabs(d[1]) : INFINITY;
     double t = 0;
     for (int it = 0; it < 1000000 && t <= tmax; ++it) {
+        /* the triangles lie at or below hf_zmax; a ray that is above it at t and not
+           descending stays above it, so it hits no further cell */
+        if (d[2] >= 0.0 && p[2] + t * d[2] > s->hf_zmax) break;
         double th = hit_cell_tris(s, i, j, p, d);
         double texit = dmin(tx, ty);
         if (th <= texit + 1e-9) return th;
