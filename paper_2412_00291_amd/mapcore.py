@@ -154,10 +154,21 @@ class CameraModel:
         return _Camera(self.width, self.height, self.fx, self.fy, self.cx, self.cy)
 
 
+_raw_stream = None  # torch's getter of the current stream's raw handle (False: not available)
+
+
 def _stream(stream):
+    """The HIP stream handle of a call: the given one, or torch's current stream (read
+    without building a Stream object when torch provides the raw getter: this runs on
+    every call of a frame)."""
     if stream is not None:
         return ctypes.c_void_p(int(stream))
+    global _raw_stream
     import torch
+    if _raw_stream is None:
+        _raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None) or False
+    if _raw_stream:
+        return ctypes.c_void_p(_raw_stream(torch.cuda.current_device()))
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -237,14 +248,14 @@ def map_integrate_labels_multi(handle, cams, labels_dev, T_wc, stream=None):
     if len(labels_dev) != n or len(T_wc) != n:
         raise ValueError("cams, labels and poses differ in length")
     carr = _cam_array(cams)
-    ptrs = np.empty(n, np.uint64)
+    ptrs = (ctypes.c_uint64 * n)()
     for i in range(n):
         c, l = cams[i], labels_dev[i]
         if l.numel() != c.width * c.height:
             raise ValueError("label image size does not match the camera model")
         ptrs[i] = _dev_ptr(l, torch.uint8, "labels")
-    T = np.ascontiguousarray(np.asarray(T_wc, np.float32).reshape(n, 16))
-    return _lib.map_integrate_labels_multi(handle, n, ctypes.cast(carr, _P), ptrs.ctypes.data, T.ctypes.data,
+    T = np.array(T_wc, dtype=np.float32).reshape(n, 16)
+    return _lib.map_integrate_labels_multi(handle, n, ctypes.cast(carr, _P), ctypes.cast(ptrs, _P), T.ctypes.data,
                                            _stream(stream))
 
 
