@@ -130,7 +130,7 @@ int om_integrate_logprobs(omap *m, int width, int height, float fx, float fy, fl
 /* A block's log-posteriors [L][512] (zero outside mode 2); returns 0 if absent. */
 int om_block_logpost(const omap *m, int bx, int by, int bz, float *LP);
 
-/* Threads this build uses: the library is built twice from this one source, plain
+/* Threads this library uses: it is built twice from this one source, plain
  * (1 thread) and with OpenMP (loops over rows, touched blocks and meshed blocks run in
  * parallel; every result is identical, only the time differs). */
 int om_threads(void);
