@@ -4,8 +4,11 @@ own kernels over several streams, and their number).
 
 Each candidate runs the same frames on freshly created maps (the maps are mutated by a
 step, so candidates never share them); the step times after the first (which also sizes
-the scratch buffers and captures the graph) are compared and the fastest candidate is
-cached in a JSON file keyed by the GPU architecture and a workload signature.
+the scratch buffers and captures the graph) are compared, by their median or their mean,
+and the fastest candidate is cached in a JSON file keyed by the GPU architecture and a
+workload signature.  The mean over every step of a workload is the figure to compare when
+its steps differ (maps that run out of frames leave later steps smaller): the schedules
+that tie on full steps need not tie on the rest.
 """
 from __future__ import annotations
 
@@ -30,11 +33,14 @@ def _arch():
     return getattr(p, "gcnArchName", p.name)
 
 
-def tune(signature, build, run_step, n_steps=3, candidates=CANDIDATES, use_cache=True):
-    """build() -> Batch on fresh maps; run_step(batch, k) runs step k (synchronous).
-    Returns (schedule, grid, timings {cand: median seconds})."""
+def tune(signature, build, run_step, n_steps=3, candidates=CANDIDATES, use_cache=True, score="median"):
+    """build() -> Batch on fresh maps; run_step(batch, k) runs step k (synchronous); steps
+    1..n_steps are timed.  score: "median" or "mean" of those step times.
+    Returns (schedule, grid, timings {cand: seconds per step by that score})."""
     import torch
-    key = f"{_arch()}|{signature}"
+    if score not in ("median", "mean"):
+        raise ValueError(f"score must be 'median' or 'mean', not {score!r}")
+    key = f"{_arch()}|{signature}|{score}"
     path = cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -59,7 +65,7 @@ def tune(signature, build, run_step, n_steps=3, candidates=CANDIDATES, use_cache
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         ts.sort()
-        timings[(sched, grid)] = ts[len(ts) // 2]
+        timings[(sched, grid)] = ts[len(ts) // 2] if score == "median" else sum(ts) / len(ts)
         for m in batch.maps:
             m.close()
         batch.close()

@@ -47,10 +47,44 @@ def test_autotuner_picks_fastest_and_caches(tmp_path, monkeypatch):
     sched, grid, timings = autotune.tune("sig-a", build, run_step, n_steps=2, candidates=list(cost))
     assert (sched, grid) == (0, 2048) and len(built) == 3
     data = json.load(open(tmp_path / "tune.json"))
-    assert data["gfx950|sig-a"]["grid"] == 2048
+    assert data["gfx950|sig-a|median"]["grid"] == 2048
     built.clear()
     assert autotune.tune("sig-a", build, run_step, candidates=list(cost))[:2] == (0, 2048)
     assert not built  # served from the cache
+
+
+def test_autotuner_mean_score_counts_every_step(tmp_path, monkeypatch):
+    """A schedule that is fastest on most steps but slow on the rest wins by the median and
+    loses by the mean; the two scores are cached apart, and an unknown score is refused."""
+    import time
+    from paper_2412_00291_amd import autotune
+    monkeypatch.setenv("MAPCORE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "_arch", lambda: "gfx950")
+
+    class _T:
+        class cuda:
+            @staticmethod
+            def synchronize():
+                pass
+    monkeypatch.setitem(__import__("sys").modules, "torch", _T)
+    # seconds per step k = 1..5: (4, 2) is fast early and slow late, (4, 16) is even
+    cost = {(4, 2): [0.001, 0.001, 0.001, 0.009, 0.009], (4, 16): [0.003] * 5}
+
+    def build():
+        return _FakeBatch()
+
+    def run_step(b, k):
+        if k > 0:
+            time.sleep(cost[b.cfg][k - 1])
+
+    sched, grid, t_med = autotune.tune("sig-b", build, run_step, n_steps=5, candidates=list(cost))
+    assert (sched, grid) == (4, 2) and t_med[(4, 2)] < t_med[(4, 16)]
+    sched, grid, t_mean = autotune.tune("sig-b", build, run_step, n_steps=5, candidates=list(cost), score="mean")
+    assert (sched, grid) == (4, 16) and t_mean[(4, 2)] > t_mean[(4, 16)]
+    data = json.load(open(tmp_path / "tune.json"))
+    assert data["gfx950|sig-b|median"]["grid"] == 2 and data["gfx950|sig-b|mean"]["grid"] == 16
+    with pytest.raises(ValueError):
+        autotune.tune("sig-b", build, run_step, candidates=list(cost), score="max")
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
