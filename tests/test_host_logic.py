@@ -110,3 +110,50 @@ def test_null_handles_are_rejected():
     _lib.map_batch_destroy(None)
     n = ctypes.c_int64(0)
     assert _lib.map_extract_mesh(None, 0, None, None, None, 0, ctypes.byref(n), None) == MAP_ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_every_entry_point_rejects_a_null_handle():
+    """Each call that takes a map rejects a NULL map before any device work (status, or -1 /
+    0 for the counting test-access calls); the calls without a map reject NULL or
+    out-of-range arguments the same way.  Runs on the host alone."""
+    import ctypes
+    from paper_2412_00291_amd import MAP_ERR_INVALID_ARG as BAD
+    from paper_2412_00291_amd.mapcore import _Quality, _lib
+    h = ctypes.c_void_p(0)
+    assert _lib.map_integrate_labels(None, None, None, None, None) == BAD
+    assert _lib.map_integrate_labels_multi(None, 0, None, None, None, None) == BAD
+    assert _lib.map_integrate_labels_lidar(None, None, None, None, None) == BAD
+    assert _lib.map_integrate_logprobs(None, None, None, None, None) == BAD
+    assert _lib.map_query_sdf(None, None, 0, None, None, None, None) == BAD
+    assert _lib.map_range_image(None, None, None, 0, 1.0, 0.0, None, None, None) == BAD
+    assert _lib.map_sdf_pose_adjoint(None, None, None, 0, 0, None, None, None, None) == BAD
+    assert _lib.map_sdf_pose_adjoint_noalloc(None, None, None, 0, 0, None, None, None, None) == BAD
+    assert _lib.map_stats(None, None) == BAD
+    assert _lib.map_profile(None, 0) == BAD
+    assert _lib.map_profile_read(None, None, None) == BAD
+    assert _lib.map_set_dirty_bitmap(None, 0) == BAD
+    assert _lib.map_set_distance(None, 0, 0.0) == BAD
+    assert _lib.map_set_label_fusion(None, 0) == BAD
+    assert _lib.map_batch_configure(None, 0, 1024, 0) == BAD
+    # test access: -1 (or 0 blocks) for no map
+    assert _lib.map_block_coords(None, None, 0) == -1
+    assert _lib.map_touched_coords(None, None, 0) == -1
+    assert _lib.map_download(None, 0, None, None, None, None, None) == -1
+    assert _lib.map_download_aux(None, 0, None, None) == -1
+    assert _lib.map_frame_normals(None, None, 0) == -1
+    assert _lib.map_read_block(None, 0, 0, 0, None, None, None, None) == 0
+    # no map: the batch needs maps and an output, the quality metrics an output and sizes
+    assert _lib.map_batch_create(None, 1, ctypes.byref(h)) == BAD
+    assert _lib.map_batch_create(None, 1, None) == BAD
+    assert "map_batch_create" in _lib.map_last_error(None).decode()
+    q = _Quality()
+    assert _lib.map_mesh_quality(None, None, 0, None, None, 0, 0.1, 19, 0, None, None, None, None, None,
+                                 None) == BAD
+    assert _lib.map_mesh_quality(None, None, -1, None, None, 0, 0.1, 19, 0, None, None, None, None,
+                                 ctypes.byref(q), None) == BAD
+    assert _lib.map_mesh_quality(None, None, 5, None, None, 0, 0.1, 19, 0, None, None, None, None,
+                                 ctypes.byref(q), None) == BAD
+    assert _lib.map_mesh_quality(None, None, 0, None, None, 0, 0.0, 19, 0, None, None, None, None,
+                                 ctypes.byref(q), None) == BAD
+    assert "mesh_quality" in _lib.map_last_error(None).decode()
