@@ -141,7 +141,9 @@ int map_extract_mesh(map_t *map, int mode, float *pos_dev, uint8_t *lab_dev,
 
 /* Work split of the per-map TSDF, label and meshing kernels (each 0 or 1): 0 = one
  * workgroup per block, 1 = one wavefront per block.  Results are identical either way;
- * only the speed differs.  Default 0, 0, 1. */
+ * only the speed differs.  Default 0, 0, 1.  The map's deferred TSDF launch, if any, is
+ * enqueued first under the old schedule (its failure is returned).  MAP_ERR_INVALID_ARG
+ * for a NULL map or a value other than 0 or 1 (the schedule is then unchanged). */
 int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
 
 /* Candidates of DIRTY meshing (Sec. IV-C.3: only the blocks changed since the last
@@ -152,7 +154,9 @@ int map_set_schedule(map_t *map, int32_t tsdf, int32_t labels, int32_t mesh);
  * extraction that follows a frame which ended at or below the threshold sweeps once more.
  * min_blocks < 0 (the default) takes the pool size one sweep round covers: 256 slots per
  * workgroup of the counting grid, 2^19 for a 2048-workgroup grid.  Results are identical
- * either way; only the speed differs. */
+ * either way; only the speed differs.  The map's deferred TSDF launch, if any, is enqueued
+ * first under the old threshold (its failure is returned).  MAP_ERR_INVALID_ARG for a
+ * NULL map. */
 int map_set_dirty_bitmap(map_t *map, int64_t min_blocks);
 
 /* Label fusion from a label range image: the scan's points labelled by a point-cloud
