@@ -40,7 +40,7 @@ def test_street_frames_lidar_and_camera_labels(torch_dev):
         assert om.integrate_labels_lidar(w.lidar, lab, f.T_wl) == oracle.OK
         T, cl, cam = f.cams[0]  # a camera after the LiDAR labels, in the same frame
         m.integrate_labels(camera_model(cam), torch.from_numpy(np.ascontiguousarray(cl)).to(dev), T)
-        om.integrate_labels(cam, cl, T)
+        assert om.integrate_labels(cam, cl, T) == oracle.OK
         assert m.sync() == 0
         _, s = m.stats()
         assert s["votes"] == om.stats()["votes"]
@@ -55,14 +55,14 @@ def test_pixel_encoding_labels_tiny_frame(torch_dev):
     f = w.frame(0, with_labels=False)
     lid = lidar_model(w.lidar)
     m.integrate_lidar(lid, torch.from_numpy(f.range).to(dev), f.T_wl)
-    om.integrate_lidar(w.lidar, f.range, f.T_wl)
+    assert om.integrate_lidar(w.lidar, f.range, f.T_wl) == oracle.OK
     R, C = w.lidar.rows, w.lidar.cols
     rows, cols = np.meshgrid(np.arange(R), np.arange(C), indexing="ij")
     lab = ((rows * 7 + cols) % (w.n_classes + 3)).astype(np.uint8)  # some labels >= L: no vote
     step_log("lidar labels: tiny frame, pixel-encoding labels")
     for _ in range(2):
         m.integrate_labels_lidar(lid, torch.from_numpy(lab).to(dev), f.T_wl)
-        om.integrate_labels_lidar(w.lidar, lab, f.T_wl)
+        assert om.integrate_labels_lidar(w.lidar, lab, f.T_wl) == oracle.OK
     assert m.sync() == 0
     _, s = m.stats()
     assert s["votes"] == om.stats()["votes"] > 1000

@@ -76,7 +76,7 @@ def test_sphere_closed_form_and_three_views(torch_dev):
     for Rm in (np.eye(3), rx, ry):
         T = synth.pose_matrix(Rm, [0.0, 0.0, 0.0])
         m.integrate_lidar(lidar_model(lidar), torch.from_numpy(rimg).to(dev), T)
-        om.integrate_lidar(lidar, rimg, T)
+        assert om.integrate_lidar(lidar, rimg, T) == oracle.OK
     compare_state(m, om)
     gm = gpu_mesh(m, 1)
     st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_ALL)

@@ -125,8 +125,8 @@ def test_bayes_matches_fp64_recursive_filter():
     codes = [(x // L ** d) % L for x in (uu, vv) for d in range(3)]
     for code in codes:
         om, = _maps(w, (oracle.LABELS_COUNTS,))
-        om.integrate_lidar(w.lidar, f.range, f.T_wl)
-        om.integrate_labels(cam, code.astype(np.uint8), T_wc)
+        assert om.integrate_lidar(w.lidar, f.range, f.T_wl) == oracle.OK
+        assert om.integrate_labels(cam, code.astype(np.uint8), T_wc) == oracle.OK
         counts_maps.append(om)
     rng = np.random.default_rng(11)
     imgs = [np.log(rng.dirichlet(np.ones(L) * 0.7, size=(H, W_))).astype(np.float32) for _ in range(5)]
@@ -190,7 +190,7 @@ def test_modes_reject_the_other_input(tiny):
     T_wc, lab, cam = f.cams[0]
     counts, bayes = _maps(w, (oracle.LABELS_COUNTS, oracle.LABELS_BAYES))
     for om in (counts, bayes):
-        om.integrate_lidar(w.lidar, f.range, f.T_wl)
+        assert om.integrate_lidar(w.lidar, f.range, f.T_wl) == oracle.OK
     assert bayes.integrate_labels(cam, lab, T_wc) == oracle.INVALID
     assert counts.integrate_logprobs(cam, synth.hard_logprob_image(lab, w.n_classes, 0.7), T_wc) == oracle.INVALID
     assert counts.set_label_fusion(3) == oracle.INVALID

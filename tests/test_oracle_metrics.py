@@ -76,7 +76,8 @@ def test_sphere_reconstruction_against_analytic_surface():
     lidar = synth.uniform_lidar(64, 720, 40.0, -40.0, 40.0)
     R = 3.0
     om = oracle.OracleMap(NU, 3 * NU, 2, 1 << 18)
-    om.integrate_lidar(lidar, synth.constant_range(lidar, R), synth.pose_matrix(np.eye(3), [0, 0, 0]))
+    T = synth.pose_matrix(np.eye(3), [0, 0, 0])
+    assert om.integrate_lidar(lidar, synth.constant_range(lidar, R), T) == oracle.OK
     st, pos, lab, keys, n = om.extract_mesh(oracle.MESH_ALL)
     V = np.unique(pos.reshape(-1, 3).astype(np.float64), axis=0)
     # ground truth: the sphere sampled densely inside the scanned band of elevations

@@ -294,7 +294,7 @@ def test_projective_mode_is_unchanged_by_the_option():
     assert b.set_distance(oracle.DIST_NONPROJECTIVE) == oracle.OK
     assert b.set_distance(oracle.DIST_PROJECTIVE) == oracle.OK
     for om in (a, b):
-        om.integrate_lidar(w.lidar, f.range, f.T_wl)
+        assert om.integrate_lidar(w.lidar, f.range, f.T_wl) == oracle.OK
     assert a.stats() == b.stats()
     for blk in a.block_coords()[::50]:
         np.testing.assert_array_equal(a.block(blk)["D"], b.block(blk)["D"])
