@@ -157,3 +157,14 @@ def test_every_entry_point_rejects_a_null_handle():
     assert _lib.map_mesh_quality(None, None, 0, None, None, 0, 0.0, 19, 0, None, None, None, None,
                                  ctypes.byref(q), None) == BAD
     assert "mesh_quality" in _lib.map_last_error(None).decode()
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says so, before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
